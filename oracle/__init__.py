@@ -1,0 +1,185 @@
+"""CPU oracle for the flux-differencing volume term -- TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the package's ``smoke()`` check and the benchmark's
+``cpu_baseline`` leg may import this package.  The product library never does,
+and this package never imports the product package: the two share no code.
+
+Python side of ``oracle.c`` (plain FP64 C, see its header for the paper
+passages it follows).  Functions take and return numpy arrays in the layout
+``u[v, e, node]`` with ``node = ix + n*iy + n*n*iz``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+FLUX = {"burgers": 0, "euler": 1, "product": 2}
+NODES = {"gl": 0, "gll": 1}
+NVAR = {"burgers": 1, "euler": 5, "product": 1}
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.oracle_nodes.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
+        L.oracle_operator.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp]
+        L.oracle_diff_matrix.argtypes = [ctypes.c_int, dp, dp]
+        L.oracle_diff_matrix.restype = None
+        L.oracle_logmean.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.oracle_logmean.restype = ctypes.c_double
+        L.oracle_flux.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, dp]
+        L.oracle_flux.restype = None
+        L.oracle_physical_flux_euler.argtypes = [dp, ctypes.c_int, ctypes.c_double, dp]
+        L.oracle_physical_flux_euler.restype = None
+        L.oracle_build_A.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.oracle_build_A.restype = None
+        for f in (L.oracle_dense_volume, L.oracle_sf_volume):
+            f.argtypes = [dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                          dp, dp, ctypes.c_double, dp]
+        L.oracle_sparsity_pattern.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip]
+        L.oracle_basis_sparse.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ip, ip, dp]
+        L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def nodes(n: int, kind: str = "gl"):
+    x = np.zeros(n); w = np.zeros(n)
+    if lib().oracle_nodes(n, NODES[kind], _dp(x), _dp(w)) != 0:
+        raise ValueError(f"bad node request n={n} kind={kind}")
+    return x, w
+
+
+def operator_1d(n: int, kind: str = "gl"):
+    """(x, w, D, Q) with Q = diag(w) D, the 1D factor of Eq. (5)."""
+    x = np.zeros(n); w = np.zeros(n); D = np.zeros((n, n)); Q = np.zeros((n, n))
+    if lib().oracle_operator(n, NODES[kind], _dp(x), _dp(w), _dp(D), _dp(Q)) != 0:
+        raise ValueError(f"bad operator request n={n} kind={kind}")
+    return x, w, D, Q
+
+
+def diff_matrix(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    D = np.zeros((len(x), len(x)))
+    lib().oracle_diff_matrix(len(x), _dp(x), _dp(D))
+    return D
+
+
+def logmean(a: float, b: float) -> float:
+    return lib().oracle_logmean(float(a), float(b))
+
+
+def flux(kind: str, uL, uR, m: int, gamma: float = 1.4) -> np.ndarray:
+    nv = NVAR[kind]
+    uL = np.ascontiguousarray(uL, dtype=np.float64).reshape(nv)
+    uR = np.ascontiguousarray(uR, dtype=np.float64).reshape(nv)
+    F = np.zeros(nv)
+    lib().oracle_flux(FLUX[kind], _dp(uL), _dp(uR), m, gamma, _dp(F))
+    return F
+
+
+def physical_flux_euler(u, m: int, gamma: float = 1.4) -> np.ndarray:
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(5)
+    F = np.zeros(5)
+    lib().oracle_physical_flux_euler(_dp(u), m, gamma, _dp(F))
+    return F
+
+
+def build_A(n: int, d: int, m: int, Q: np.ndarray, w: np.ndarray) -> np.ndarray:
+    N = n ** d
+    Q = np.ascontiguousarray(Q, dtype=np.float64); w = np.ascontiguousarray(w, dtype=np.float64)
+    A = np.zeros((N, N))
+    lib().oracle_build_A(n, d, m, _dp(Q), _dp(w), _dp(A))
+    return A
+
+
+def _volume(fn, u, n, d, flux_kind, Q, w, gamma):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    nv = NVAR[flux_kind]
+    N = n ** d
+    if u.ndim != 3 or u.shape[0] != nv or u.shape[2] != N:
+        raise ValueError(f"u must be ({nv}, E, {N}), got {u.shape}")
+    E = u.shape[1]
+    Q = np.ascontiguousarray(Q, dtype=np.float64); w = np.ascontiguousarray(w, dtype=np.float64)
+    out = np.zeros_like(u)
+    rc = fn(_dp(u), E, n, d, FLUX[flux_kind], _dp(Q), _dp(w), gamma, _dp(out))
+    if rc != 0:
+        raise ValueError("oracle rejected arguments")
+    return out
+
+
+def dense_volume(u, n, d, flux_kind, Q=None, w=None, nodes_kind="gl", gamma=1.4):
+    """The definition y = sum_m (A_m o F_m) 1 over all n^(2d) pairs."""
+    if Q is None or w is None:
+        _, w0, _, Q0 = operator_1d(n, nodes_kind)
+        Q = Q0 if Q is None else Q
+        w = w0 if w is None else w
+    return _volume(lib().oracle_dense_volume, u, n, d, flux_kind, Q, w, gamma)
+
+
+def sf_volume(u, n, d, flux_kind, Q=None, w=None, nodes_kind="gl", gamma=1.4):
+    """The paper's CPU method (Algorithms 1-2, then the Hadamard product)."""
+    if Q is None or w is None:
+        _, w0, _, Q0 = operator_1d(n, nodes_kind)
+        Q = Q0 if Q is None else Q
+        w = w0 if w is None else w
+    return _volume(lib().oracle_sf_volume, u, n, d, flux_kind, Q, w, gamma)
+
+
+def sparsity_pattern(n: int, d: int):
+    rows = np.zeros((n ** (d + 1), d), dtype=np.int32)
+    cols = np.zeros((n ** (d + 1), d), dtype=np.int32)
+    if lib().oracle_sparsity_pattern(n, d, _ip(rows), _ip(cols)) != 0:
+        raise ValueError("d must be 2 or 3")
+    return rows, cols
+
+
+def basis_sparse(n: int, d: int, Q: np.ndarray, w: np.ndarray):
+    rows, cols = sparsity_pattern(n, d)
+    Q = np.ascontiguousarray(Q, dtype=np.float64); w = np.ascontiguousarray(w, dtype=np.float64)
+    bs = np.zeros((d, n ** d, n))
+    lib().oracle_basis_sparse(n, d, _dp(Q), _dp(w), _ip(rows), _ip(cols), _dp(bs))
+    return bs
+
+
+def num_threads() -> int:
+    return lib().oracle_num_threads()
+
+
+def set_num_threads(t: int) -> None:
+    lib().oracle_set_num_threads(int(t))

@@ -1,0 +1,452 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 CPU implementation of the flux-differencing volume term
+ *
+ *     y = sum_m (A_m o F_m) 1 ,
+ *
+ * used only by the test-suite, by the package's smoke check and by the
+ * benchmark's CPU-baseline leg.  Nothing in the product library links, loads
+ * or calls this file, and this file shares no code with the product library.
+ *
+ * Paper: Cicchino & Nadarajah, "Scalable Evaluation of Hadamard Products with
+ * Tensor Product Basis for Entropy-Stable High-Order Methods".
+ *
+ *   - Eq. (1) and Eq. (3): the Hadamard product of a Kronecker-structured
+ *     operator with a dense n^d x n^d matrix C.
+ *   - Eq. (5): the weighted derivative operator W (x) (W dl) (x) W, i.e. in
+ *     direction m the dense 1D factor Q = W D sits in position m and the
+ *     diagonal weight matrix W sits in every other position.
+ *   - Section 2 (implementation paragraph): the x index runs fastest, then y,
+ *     then z.
+ *   - Algorithms 1 and 2: the sparsity pattern and basis assembly of the
+ *     paper's own CPU method; oracle_sparsity_pattern / oracle_basis_sparse /
+ *     oracle_sf_volume below restate those steps for d = 3 (and the d = 2
+ *     form that follows from Eq. (2)).
+ *
+ * The primary oracle is oracle_dense_volume: it builds every A_m as an
+ * explicit Kronecker product (n^d x n^d), evaluates the two-point flux on ALL
+ * n^(2d) node pairs and sums the Hadamard product row by row, with no
+ * zero-skipping.  oracle_sf_volume is the paper's O(n^(d+1)) CPU method, kept
+ * as an independent cross-check and a CPU speed baseline.
+ *
+ * Readings taken where the paper is silent (each also listed in the design
+ * notes): nodes on [-1,1]; Q = W D (Eq. (5) carries W on the derivative
+ * direction); no factor 2 in front of the Hadamard sum; the Chandrashekar
+ * flux (cited in the Results section but not printed) in its published form,
+ * with the logarithmic mean evaluated as (b-a)/log1p((b-a)/a).
+ *
+ * Layout of every state / output array:
+ *     u[v * E * N + e * N + node],  node = ix + n*iy + n*n*iz,  N = n^d.
+ * Euler variables in order (rho, rho*u, rho*v, rho*w, E).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC oracle.c -lm
+ * (no FMA contraction: every rounding is the one written here).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { OR_FLUX_BURGERS = 0, OR_FLUX_EULER = 1, OR_FLUX_PRODUCT = 2 };
+enum { OR_NODES_GL = 0, OR_NODES_GLL = 1 };
+
+#define OR_PI 3.14159265358979323846264338327950288
+
+/* ------------------------------------------------------------------------ */
+/* 1D Legendre polynomials by the three-term recurrence                      */
+/*   (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1},  P'_{k+1} = P'_{k-1} + (2k+1) P_k */
+/* ------------------------------------------------------------------------ */
+static void legendre(int N, double x, double *P, double *dP)
+{
+    double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0;
+    if (N == 0) { *P = 1.0; *dP = 0.0; return; }
+    for (int k = 1; k < N; ++k) {
+        double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+        double d2 = d0 + (2.0 * k + 1.0) * p1;
+        p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+    }
+    *P = p1; *dP = d1;
+}
+
+/* Gauss-Legendre: the n roots of P_n, ascending, weights
+ * w_i = 2 / ((1 - x_i^2) P_n'(x_i)^2).  Newton from Chebyshev guesses. */
+int oracle_gauss_legendre(int n, double *x, double *w)
+{
+    if (n < 1) return -1;
+    for (int i = 0; i < n; ++i) {
+        double z = cos(OR_PI * (i + 0.75) / (n + 0.5));   /* descending guesses */
+        for (int it = 0; it < 100; ++it) {
+            double P, dP;
+            legendre(n, z, &P, &dP);
+            double dz = P / dP;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        double P, dP;
+        legendre(n, z, &P, &dP);
+        x[n - 1 - i] = z;
+        w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dP * dP);
+    }
+    return 0;
+}
+
+/* Gauss-Lobatto-Legendre with n points, N = n-1: x = -1, the roots of P_N',
+ * +1; weights w_i = 2 / (N (N+1) P_N(x_i)^2).  The interior roots come from
+ * Newton on P_N' with P_N'' taken from Legendre's equation
+ *   (1 - x^2) P_N'' = 2 x P_N' - N (N+1) P_N. */
+int oracle_gauss_lobatto(int n, double *x, double *w)
+{
+    if (n < 2) return -1;
+    int N = n - 1;
+    x[0] = -1.0; x[N] = 1.0;
+    for (int i = 1; i < N; ++i) {
+        double z = -cos(OR_PI * i / N);                      /* ascending guesses */
+        for (int it = 0; it < 100; ++it) {
+            double P, dP;
+            legendre(N, z, &P, &dP);
+            double d2P = (2.0 * z * dP - N * (N + 1.0) * P) / (1.0 - z * z);
+            double dz = dP / d2P;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+    }
+    for (int i = 0; i <= N; ++i) {
+        double P, dP;
+        legendre(N, x[i], &P, &dP);
+        w[i] = 2.0 / (N * (N + 1.0) * P * P);
+    }
+    return 0;
+}
+
+int oracle_nodes(int n, int kind, double *x, double *w)
+{
+    if (kind == OR_NODES_GL) return oracle_gauss_legendre(n, x, w);
+    if (kind == OR_NODES_GLL) return oracle_gauss_lobatto(n, x, w);
+    return -1;
+}
+
+/* Collocated Lagrange derivative D_ij = l_j'(x_i) in barycentric form:
+ * lambda_j = 1 / prod_{k != j} (x_j - x_k),
+ * D_ij = (lambda_j / lambda_i) / (x_i - x_j)  (i != j),
+ * D_ii = -sum_{j != i} D_ij  (so that D 1 = 0 up to rounding). */
+void oracle_diff_matrix(int n, const double *x, double *D)
+{
+    double *lam = (double *)malloc(sizeof(double) * n);
+    for (int j = 0; j < n; ++j) {
+        double p = 1.0;
+        for (int k = 0; k < n; ++k)
+            if (k != j) p *= (x[j] - x[k]);
+        lam[j] = 1.0 / p;
+    }
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            D[i * n + j] = (lam[j] / lam[i]) / (x[i] - x[j]);
+            s += D[i * n + j];
+        }
+        D[i * n + i] = -s;
+    }
+    free(lam);
+}
+
+/* The 1D operator of Eq. (5): Q = W D with W = diag(w). Row-major n x n. */
+int oracle_operator(int n, int kind, double *x, double *w, double *D, double *Q)
+{
+    if (oracle_nodes(n, kind, x, w) != 0) return -1;
+    oracle_diff_matrix(n, x, D);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Q[i * n + j] = w[i] * D[i * n + j];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Two-point fluxes f_m(u_L, u_R)                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Logarithmic mean (a - b) / (ln a - ln b), written as
+ * (b - a) / log1p((b - a) / a); equal arguments return a. */
+double oracle_logmean(double a, double b)
+{
+    if (a == b) return a;
+    return (b - a) / log1p((b - a) / a);
+}
+
+/* Entropy-conserving Burgers flux for u_t + (u^2/2)_x = 0: (a^2 + ab + b^2)/6. */
+double oracle_flux_burgers(double a, double b) { return (a * a + a * b + b * b) / 6.0; }
+
+/* The rank-one workload of the Results section: C_ij = c_i c_j. */
+double oracle_flux_product(double a, double b) { return a * b; }
+
+/* Chandrashekar's kinetic-energy-preserving, entropy-conserving flux for the
+ * 3D compressible Euler equations (the volume flux named in the Results
+ * section), direction m, conserved inputs (rho, rho u, rho v, rho w, E).
+ *   beta = rho / (2 p),  {{a}} = (a_L + a_R)/2,  a^ln = logarithmic mean,
+ *   F^rho   = rho^ln {{v_m}},
+ *   F^rhov_k = F^rho {{v_k}} + p_hat delta_km,  p_hat = {{rho}} / (2 {{beta}}),
+ *   F^E     = F^rho [ 1/(2 (gamma-1) beta^ln) - {{|v|^2}}/2 ] + sum_k {{v_k}} F^rhov_k. */
+void oracle_flux_euler(const double *uL, const double *uR, int m, double gamma, double *F)
+{
+    double rl = uL[0], rr = uR[0];
+    double vl[3], vr[3], vbar[3];
+    for (int k = 0; k < 3; ++k) { vl[k] = uL[1 + k] / rl; vr[k] = uR[1 + k] / rr; }
+    double ql = vl[0] * vl[0] + vl[1] * vl[1] + vl[2] * vl[2];
+    double qr = vr[0] * vr[0] + vr[1] * vr[1] + vr[2] * vr[2];
+    double pl = (gamma - 1.0) * (uL[4] - 0.5 * rl * ql);
+    double pr = (gamma - 1.0) * (uR[4] - 0.5 * rr * qr);
+    double bl = rl / (2.0 * pl), br = rr / (2.0 * pr);
+
+    double rho_ln = oracle_logmean(rl, rr);
+    double beta_ln = oracle_logmean(bl, br);
+    double rho_avg = 0.5 * (rl + rr);
+    double beta_avg = 0.5 * (bl + br);
+    double p_hat = rho_avg / (2.0 * beta_avg);
+    double q_avg = 0.5 * (ql + qr);
+    for (int k = 0; k < 3; ++k) vbar[k] = 0.5 * (vl[k] + vr[k]);
+
+    F[0] = rho_ln * vbar[m];
+    for (int k = 0; k < 3; ++k) F[1 + k] = F[0] * vbar[k] + (k == m ? p_hat : 0.0);
+    F[4] = F[0] * (1.0 / (2.0 * (gamma - 1.0) * beta_ln) - 0.5 * q_avg)
+         + vbar[0] * F[1] + vbar[1] * F[2] + vbar[2] * F[3];
+}
+
+/* Physical Euler flux f_m(u) (the consistency target f_m(u,u) = f_m(u)). */
+void oracle_physical_flux_euler(const double *u, int m, double gamma, double *F)
+{
+    double r = u[0];
+    double v[3] = { u[1] / r, u[2] / r, u[3] / r };
+    double p = (gamma - 1.0) * (u[4] - 0.5 * r * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+    F[0] = r * v[m];
+    for (int k = 0; k < 3; ++k) F[1 + k] = r * v[m] * v[k] + (k == m ? p : 0.0);
+    F[4] = (u[4] + p) * v[m];
+}
+
+static int flux_nvar(int flux) { return flux == OR_FLUX_EULER ? 5 : 1; }
+
+/* f_m(u_L, u_R) for any supported flux; uL, uR point to nvar values. */
+void oracle_flux(int flux, const double *uL, const double *uR, int m, double gamma, double *F)
+{
+    if (flux == OR_FLUX_EULER) oracle_flux_euler(uL, uR, m, gamma, F);
+    else if (flux == OR_FLUX_BURGERS) F[0] = oracle_flux_burgers(uL[0], uR[0]);
+    else F[0] = oracle_flux_product(uL[0], uR[0]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense definition: y = sum_m (A_m o F_m) 1 over all n^(2d) pairs            */
+/* ------------------------------------------------------------------------ */
+
+/* Kronecker product K = A (x) B, A ra x ca, B rb x cb, all row-major. */
+static void kron(const double *A, int ra, int ca, const double *B, int rb, int cb, double *K)
+{
+    int kc = ca * cb;
+    for (int i = 0; i < ra; ++i)
+        for (int j = 0; j < ca; ++j)
+            for (int k = 0; k < rb; ++k)
+                for (int l = 0; l < cb; ++l)
+                    K[(size_t)(i * rb + k) * kc + (j * cb + l)] = A[i * ca + j] * B[k * cb + l];
+}
+
+/* A_m for direction m (0 = x, 1 = y, 2 = z): the Kronecker product of d
+ * one-dimensional factors, slowest index first (z (x) y (x) x), so that the
+ * node index ix + n iy + n^2 iz of the paper's ordering is the row index.
+ * The factor acting on direction m is Q, the others are W = diag(w). */
+void oracle_build_A(int n, int d, int m, const double *Q, const double *w, double *A)
+{
+    int N = 1;
+    for (int k = 0; k < d; ++k) N *= n;
+    double *Wm = (double *)calloc((size_t)n * n, sizeof(double));
+    for (int i = 0; i < n; ++i) Wm[i * n + i] = w[i];
+    double *cur = (double *)malloc(sizeof(double) * (size_t)N * N);
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)N * N);
+    int size = n;
+    memcpy(cur, (d - 1 == m) ? Q : Wm, sizeof(double) * n * n);
+    for (int k = d - 2; k >= 0; --k) {
+        const double *f = (k == m) ? Q : Wm;
+        kron(cur, size, size, f, n, n, tmp);
+        size *= n;
+        memcpy(cur, tmp, sizeof(double) * (size_t)size * size);
+    }
+    memcpy(A, cur, sizeof(double) * (size_t)N * N);
+    free(Wm); free(cur); free(tmp);
+}
+
+/* The dense oracle.  Q (n x n) and w (n) are the 1D operator and weights
+ * (normally from oracle_operator; any override may be passed).  Returns 0,
+ * or -1 on bad arguments.  OpenMP over elements; each element is summed in
+ * the fixed order m, then j. */
+int oracle_dense_volume(const double *u, long E, int n, int d, int flux,
+                        const double *Q, const double *w, double gamma, double *out)
+{
+    if (!u || !out || !Q || !w || E < 0 || n < 1 || d < 1 || d > 3) return -1;
+    int N = 1;
+    for (int k = 0; k < d; ++k) N *= n;
+    int nv = flux_nvar(flux);
+    double *A = (double *)malloc(sizeof(double) * (size_t)d * N * N);
+    for (int m = 0; m < d; ++m) oracle_build_A(n, d, m, Q, w, A + (size_t)m * N * N);
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long e = 0; e < E; ++e) {
+        double *ue = (double *)malloc(sizeof(double) * (size_t)N * nv);
+        double *ye = (double *)calloc((size_t)N * nv, sizeof(double));
+        double F[5];
+        for (int i = 0; i < N; ++i)
+            for (int v = 0; v < nv; ++v) ue[i * nv + v] = u[(size_t)v * E * N + (size_t)e * N + i];
+        for (int m = 0; m < d; ++m) {
+            const double *Am = A + (size_t)m * N * N;
+            for (int i = 0; i < N; ++i)
+                for (int j = 0; j < N; ++j) {
+                    oracle_flux(flux, ue + i * nv, ue + j * nv, m, gamma, F);
+                    double a = Am[(size_t)i * N + j];
+                    for (int v = 0; v < nv; ++v) ye[i * nv + v] += a * F[v];
+                }
+        }
+        for (int i = 0; i < N; ++i)
+            for (int v = 0; v < nv; ++v) out[(size_t)v * E * N + (size_t)e * N + i] = ye[i * nv + v];
+        free(ue); free(ye);
+    }
+    free(A);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The paper's CPU method (Algorithms 1 and 2 plus the "third step")         */
+/* ------------------------------------------------------------------------ */
+
+/* Algorithm 1 restated.  rows and cols are n^(d+1) x d integer arrays
+ * (row-major: entry [idx * d + m]).  For d = 3 the loop variables are
+ * (i, j, k, l) = (z, y, x, line position): the row node has indices
+ * (x, y, z) = (k, j, i); the direction-m column node replaces the m-th index
+ * of the row node by l.  For d = 2 (Eq. (2)) the loop is (j, k, l) with row
+ * node (x, y) = (k, j). */
+int oracle_sparsity_pattern(int n, int d, int *rows, int *cols)
+{
+    if (d == 3) {
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                for (int k = 0; k < n; ++k)
+                    for (int l = 0; l < n; ++l) {
+                        int idx = ((i * n + j) * n + k) * n + l;
+                        int row = i * n * n + j * n + k;
+                        for (int m = 0; m < 3; ++m) rows[idx * 3 + m] = row;
+                        cols[idx * 3 + 0] = i * n * n + j * n + l;   /* x: replace k */
+                        cols[idx * 3 + 1] = i * n * n + l * n + k;   /* y: replace j */
+                        cols[idx * 3 + 2] = l * n * n + j * n + k;   /* z: replace i */
+                    }
+        return 0;
+    }
+    if (d == 2) {
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k)
+                for (int l = 0; l < n; ++l) {
+                    int idx = (j * n + k) * n + l;
+                    int row = j * n + k;
+                    rows[idx * 2 + 0] = row; rows[idx * 2 + 1] = row;
+                    cols[idx * 2 + 0] = j * n + l;               /* x: replace k */
+                    cols[idx * 2 + 1] = l * n + k;               /* y: replace j */
+                }
+        return 0;
+    }
+    return -1;
+}
+
+/* Algorithm 2 restated: Basis_Sparse[m][row][l] = Q[row_m][col_m] times the
+ * weights of the row node's other indices, where row_m / col_m are the
+ * direction-m digits of the row and column node indices and l (the
+ * "counter") is the position along the line, i.e. idx mod n.  Output is
+ * d x n^d x n, row-major. */
+int oracle_basis_sparse(int n, int d, const double *Q, const double *w,
+                        const int *rows, const int *cols, double *bs)
+{
+    if (d != 2 && d != 3) return -1;
+    int N = 1;
+    for (int k = 0; k < d; ++k) N *= n;
+    int total = N * n;
+    for (int idx = 0; idx < total; ++idx) {
+        int l = idx % n;
+        for (int m = 0; m < d; ++m) {
+            int r = rows[idx * d + m], c = cols[idx * d + m];
+            /* digits of the row node and column node in each direction */
+            int rd[3] = { r % n, (r / n) % n, r / (n * n) };
+            int cd[3] = { c % n, (c / n) % n, c / (n * n) };
+            double v = Q[rd[m] * n + cd[m]];
+            for (int k = 0; k < d; ++k)
+                if (k != m) v *= w[rd[k]];
+            bs[((size_t)m * N + r) * n + l] = v;
+        }
+    }
+    return 0;
+}
+
+/* The paper's method end to end for a whole mesh: the flux matrices C_m are
+ * assembled with the same sparsity pattern (C_m[row][l] = f_m(u_row,
+ * u_col)), the Hadamard product of the n^d x n matrices is taken, and each
+ * row is summed over l and over m.  O(d n^(d+1)) flux evaluations per
+ * element.  Only d = 2, 3. */
+int oracle_sf_volume(const double *u, long E, int n, int d, int flux,
+                     const double *Q, const double *w, double gamma, double *out)
+{
+    if (!u || !out || !Q || !w || E < 0 || n < 1 || (d != 2 && d != 3)) return -1;
+    int N = 1;
+    for (int k = 0; k < d; ++k) N *= n;
+    int total = N * n;
+    int nv = flux_nvar(flux);
+    int *rows = (int *)malloc(sizeof(int) * (size_t)total * d);
+    int *cols = (int *)malloc(sizeof(int) * (size_t)total * d);
+    double *bs = (double *)malloc(sizeof(double) * (size_t)d * total);
+    oracle_sparsity_pattern(n, d, rows, cols);
+    oracle_basis_sparse(n, d, Q, w, rows, cols, bs);
+
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long e = 0; e < E; ++e) {
+        double *ue = (double *)malloc(sizeof(double) * (size_t)N * nv);
+        double *C = (double *)malloc(sizeof(double) * (size_t)d * total * nv);
+        double F[5];
+        for (int i = 0; i < N; ++i)
+            for (int v = 0; v < nv; ++v) ue[i * nv + v] = u[(size_t)v * E * N + (size_t)e * N + i];
+        /* assemble C_m (n^d x n per variable) on the sparsity pattern */
+        for (int idx = 0; idx < total; ++idx) {
+            int l = idx % n;
+            for (int m = 0; m < d; ++m) {
+                int r = rows[idx * d + m], c = cols[idx * d + m];
+                oracle_flux(flux, ue + r * nv, ue + c * nv, m, gamma, F);
+                for (int v = 0; v < nv; ++v) C[(((size_t)m * N + r) * n + l) * nv + v] = F[v];
+            }
+        }
+        /* third step: Hadamard product of the dense n^d x n matrices, row sums */
+        for (int r = 0; r < N; ++r)
+            for (int v = 0; v < nv; ++v) {
+                double s = 0.0;
+                for (int m = 0; m < d; ++m)
+                    for (int l = 0; l < n; ++l)
+                        s += bs[((size_t)m * N + r) * n + l] * C[(((size_t)m * N + r) * n + l) * nv + v];
+                out[(size_t)v * E * N + (size_t)e * N + r] = s;
+            }
+        free(ue); free(C);
+    }
+    free(rows); free(cols); free(bs);
+    return 0;
+}
+
+/* Thread count OpenMP will use (1 without OpenMP). */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_num_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}

@@ -1,0 +1,166 @@
+"""Seeded synthetic workloads for the volume term (inputs only).
+
+This module draws states; it holds none of the volume term's arithmetic.  The
+only formula here is the ideal-gas equation of state used to turn drawn
+primitive variables into the conserved variables that both the library and
+the CPU oracle read:  E = p/(gamma-1) + rho |v|^2 / 2.
+
+Workload recipe (all FP64, layout u[v, e, node], node = ix + n*iy + n*n*iz):
+
+* burgers2d_n4_gll_e64: 2D Burgers, n = 4 Gauss-Lobatto nodes, 64 elements,
+  u ~ U[-1, 1], seed 1.
+* euler3d_n4_gl_e4096: 3D Euler, n = 4 Gauss-Legendre nodes, 4096 elements,
+  rho ~ U[0.5, 1.5], each velocity component ~ U[-0.5, 0.5],
+  p ~ U[0.5, 1.5] per node, seed 2.
+* euler3d_n8_gl_e32768: as above with n = 8, 32768 elements, seed 3; a
+  seeded permutation picks round(0.1 E) elements that are set to one
+  constant (free-stream) state drawn from the same distributions, so every
+  pair inside them is exactly equal.
+* serving mix: meshes with p ~ U{2..7} (n = p + 1), E log-uniform in
+  [512, 32768], states as the n = 4 workload, seed 5000 + k for mesh k;
+  Poisson arrivals from seed 5.
+
+The random numbers come from numpy's PCG64 (default_rng).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    flux: str          # "burgers" | "euler" | "product"
+    d: int
+    n: int
+    nodes: str         # "gl" | "gll"
+    E: int
+    seed: int
+    freestream_frac: float = 0.0
+    precision: str = "fp64"
+
+    @property
+    def nvar(self) -> int:
+        return 5 if self.flux == "euler" else 1
+
+    @property
+    def nodes_per_elem(self) -> int:
+        return self.n ** self.d
+
+    @property
+    def dof(self) -> int:
+        return self.E * self.nodes_per_elem * self.nvar
+
+    def state(self) -> np.ndarray:
+        return make_state(self)
+
+
+WORKLOADS = {
+    "burgers2d_n4_gll_e64": Workload("burgers2d_n4_gll_e64", "burgers", 2, 4, "gll", 64, 1),
+    "euler3d_n4_gl_e4096": Workload("euler3d_n4_gl_e4096", "euler", 3, 4, "gl", 4096, 2),
+    "euler3d_n8_gl_e32768": Workload("euler3d_n8_gl_e32768", "euler", 3, 8, "gl", 32768, 3, 0.1),
+    "euler3d_n8_gl_e32768_fp32split": Workload("euler3d_n8_gl_e32768_fp32split", "euler", 3, 8, "gl",
+                                               32768, 3, 0.1, "fp32_split"),
+}
+
+
+def primitives_to_conserved(rho, vel, p, gamma=GAMMA):
+    """(rho, v[3], p) -> (rho, rho v[3], E) with E = p/(gamma-1) + rho |v|^2 / 2."""
+    q = vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2]
+    return np.stack([rho, rho * vel[0], rho * vel[1], rho * vel[2], p / (gamma - 1.0) + 0.5 * rho * q])
+
+
+def euler_state(E: int, n: int, seed: int, freestream_frac: float = 0.0, gamma: float = GAMMA,
+                d: int = 3) -> np.ndarray:
+    """Conserved Euler states (5, E, n^d) drawn per node; optional free-stream elements."""
+    N = n ** d
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.5, 1.5, size=(E, N))
+    vel = rng.uniform(-0.5, 0.5, size=(3, E, N))
+    p = rng.uniform(0.5, 1.5, size=(E, N))
+    if freestream_frac > 0.0 and E > 0:
+        k = int(round(freestream_frac * E))
+        idx = np.sort(rng.permutation(E)[:k])
+        rho_c = rng.uniform(0.5, 1.5, size=k)
+        vel_c = rng.uniform(-0.5, 0.5, size=(3, k))
+        p_c = rng.uniform(0.5, 1.5, size=k)
+        rho[idx, :] = rho_c[:, None]
+        vel[:, idx, :] = vel_c[:, :, None]
+        p[idx, :] = p_c[:, None]
+    return np.ascontiguousarray(primitives_to_conserved(rho, vel, p, gamma))
+
+
+def _freestream_idx(E: int, n: int, seed: int, freestream_frac: float, d: int = 3) -> np.ndarray:
+    N = n ** d
+    rng = np.random.default_rng(seed)
+    rng.uniform(0.5, 1.5, size=(E, N))
+    rng.uniform(-0.5, 0.5, size=(3, E, N))
+    rng.uniform(0.5, 1.5, size=(E, N))
+    k = int(round(freestream_frac * E))
+    return np.sort(rng.permutation(E)[:k])
+
+
+def freestream_index(w: Workload) -> np.ndarray:
+    if w.freestream_frac <= 0.0:
+        return np.zeros(0, dtype=np.int64)
+    return _freestream_idx(w.E, w.n, w.seed, w.freestream_frac, w.d)
+
+
+def scalar_state(E: int, n: int, d: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """Scalar nodal states (1, E, n^d) ~ U[lo, hi]."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=(1, E, n ** d))
+
+
+def make_state(w: Workload) -> np.ndarray:
+    if w.flux == "euler":
+        return euler_state(w.E, w.n, w.seed, w.freestream_frac, d=w.d)
+    if w.flux == "product":
+        return scalar_state(w.E, w.n, w.d, w.seed, 1e-8, 30.0)
+    return scalar_state(w.E, w.n, w.d, w.seed)
+
+
+def sample_elements(E: int, k: int, seed: int, must_include=()) -> np.ndarray:
+    """A seeded sorted sample of k element indices (plus any must_include)."""
+    rng = np.random.default_rng(seed)
+    k = min(k, E)
+    pick = set(rng.choice(E, size=k, replace=False).tolist())
+    pick.update(int(i) for i in must_include)
+    return np.array(sorted(pick), dtype=np.int64)
+
+
+@dataclass
+class MeshSpec:
+    mesh_id: int
+    n: int
+    E: int
+    seed: int
+
+
+def serving_meshes(count: int = 64, base_seed: int = 5000, e_lo: int = 512, e_hi: int = 32768,
+                   p_lo: int = 2, p_hi: int = 7) -> list:
+    """Mesh k: p ~ U{p_lo..p_hi}, n = p + 1, E = round(exp(U[ln e_lo, ln e_hi])), seed base+k."""
+    out = []
+    for k in range(count):
+        rng = np.random.default_rng(base_seed + k)
+        p = int(rng.integers(p_lo, p_hi + 1))
+        E = int(round(math.exp(rng.uniform(math.log(e_lo), math.log(e_hi)))))
+        out.append(MeshSpec(k, p + 1, E, base_seed + k))
+    return out
+
+
+def serving_mesh_state(spec: MeshSpec) -> np.ndarray:
+    return euler_state(spec.E, spec.n, spec.seed)
+
+
+def poisson_arrivals(rate_hz: float, count: int, n_meshes: int, seed: int = 5):
+    """(arrival times in s, mesh index per request) for a Poisson stream."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_hz, size=count)
+    mesh = rng.integers(0, n_meshes, size=count)
+    return np.cumsum(gaps), mesh

@@ -1,0 +1,133 @@
+"""Pins of the oracle's two-point fluxes and logarithmic mean.
+
+The paper names Chandrashekar's flux for the volume term (Results section)
+without printing it, so the oracle's flux is pinned by the identities that
+define an entropy-conservative, kinetic-energy-preserving flux: symmetry,
+consistency with the physical flux, Tadmor's entropy-conservation identity
+(which, given the density flux and the pressure mean, fixes the energy flux
+uniquely), and the kinetic-energy-preserving momentum structure.  The
+logarithmic mean is pinned against mpmath.
+"""
+import numpy as np
+import pytest
+
+GAMMA = 1.4
+
+
+def _rand_states(rng, k):
+    from paper_2306_11665_amd import workloads as W
+    rho = rng.uniform(0.5, 1.5, k)
+    vel = rng.uniform(-0.5, 0.5, (3, k))
+    p = rng.uniform(0.5, 1.5, k)
+    return W.primitives_to_conserved(rho, vel, p, GAMMA).T   # (k, 5)
+
+
+def _entropy_vars(u, g=GAMMA):
+    r = u[0]; v = u[1:4] / r
+    p = (g - 1) * (u[4] - 0.5 * r * v @ v)
+    s = np.log(p) - g * np.log(r)
+    beta = r / (2 * p)
+    return np.r_[(g - s) / (g - 1) - beta * (v @ v), 2 * beta * v, -2 * beta], r * v
+
+
+def test_logmean_mpmath(orc):
+    import mpmath as mp
+    mp.mp.dps = 40
+    rng = np.random.default_rng(3)
+    worst = 0.0
+    for rel in [0.0, 1e-15, 1e-12, 1e-9, 1e-6, 1e-4, 1e-2, 0.3, 0.9]:
+        for _ in range(40):
+            a = rng.uniform(0.1, 10.0)
+            b = a * (1 + rel * rng.uniform(-1, 1))
+            if rel == 0.9:
+                b = a * float(np.exp(rng.uniform(-3, 3)))   # wide ratios too
+            got = orc.logmean(a, b)
+            A, B = mp.mpf(a), mp.mpf(b)
+            ref = A if A == B else (A - B) / (mp.log(A) - mp.log(B))
+            worst = max(worst, abs(float((got - ref) / ref)))
+    assert worst < 8 * np.finfo(float).eps, worst
+
+
+def test_logmean_special_values(orc):
+    assert orc.logmean(2.0, 2.0) == 2.0
+    assert orc.logmean(1.0, np.e) == pytest.approx(np.e - 1.0, rel=1e-15)
+    assert orc.logmean(3.0, 5.0) == pytest.approx(orc.logmean(5.0, 3.0), rel=1e-15)
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_euler_flux_symmetric_and_consistent(orc, m):
+    rng = np.random.default_rng(10 + m)
+    S = _rand_states(rng, 50)
+    for i in range(49):
+        F1 = orc.flux("euler", S[i], S[i + 1], m, GAMMA)
+        F2 = orc.flux("euler", S[i + 1], S[i], m, GAMMA)
+        np.testing.assert_allclose(F1, F2, rtol=4e-16, atol=4e-16)
+        Fc = orc.flux("euler", S[i], S[i], m, GAMMA)
+        Fp = orc.physical_flux_euler(S[i], m, GAMMA)
+        np.testing.assert_allclose(Fc, Fp, rtol=0, atol=2e-16 * max(1, np.abs(Fp).max()) * 4)
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_euler_flux_entropy_conservation(orc, m):
+    """Tadmor: (v_R - v_L) . F_m = psi_m(R) - psi_m(L), psi_m = rho v_m."""
+    rng = np.random.default_rng(20 + m)
+    S = _rand_states(rng, 60)
+    for i in range(0, 60, 2):
+        uL, uR = S[i], S[i + 1]
+        F = orc.flux("euler", uL, uR, m, GAMMA)
+        vL, psiL = _entropy_vars(uL); vR, psiR = _entropy_vars(uR)
+        lhs = (vR - vL) @ F
+        assert abs(lhs - (psiR[m] - psiL[m])) < 1e-14, (lhs, psiR[m] - psiL[m])
+
+
+def test_euler_flux_kinetic_energy_structure(orc):
+    """Momentum flux = mass flux times the mean velocity, plus a pressure mean
+    on the normal component only (the kinetic-energy-preserving form)."""
+    rng = np.random.default_rng(30)
+    S = _rand_states(rng, 20)
+    for i in range(19):
+        uL, uR = S[i], S[i + 1]
+        vbar = 0.5 * (uL[1:4] / uL[0] + uR[1:4] / uR[0])
+        pis = []
+        for m in range(3):
+            F = orc.flux("euler", uL, uR, m, GAMMA)
+            assert F[0] == pytest.approx(orc.logmean(uL[0], uR[0]) * vbar[m], rel=1e-14)
+            for k in range(3):
+                resid = F[1 + k] - F[0] * vbar[k]
+                if k != m:
+                    assert abs(resid) < 1e-15
+                else:
+                    pis.append(resid)
+        # the pressure mean is the same in every direction
+        assert np.ptp(pis) < 1e-15
+
+
+def test_euler_flux_energy_unique_given_mass_and_pressure(orc):
+    """With F^rho and the momentum flux fixed, the entropy identity is linear in
+    F^E with coefficient (v5_R - v5_L) = -2 (beta_R - beta_L) != 0, so F^E is
+    the unique solution; recover it from the identity and compare."""
+    rng = np.random.default_rng(40)
+    S = _rand_states(rng, 20)
+    for i in range(19):
+        uL, uR = S[i], S[i + 1]
+        vL, psiL = _entropy_vars(uL); vR, psiR = _entropy_vars(uR)
+        for m in range(3):
+            F = orc.flux("euler", uL, uR, m, GAMMA)
+            dv = vR - vL
+            FE = (psiR[m] - psiL[m] - dv[:4] @ F[:4]) / dv[4]
+            assert F[4] == pytest.approx(FE, rel=1e-11, abs=1e-13)
+
+
+def test_burgers_flux_pins(orc):
+    rng = np.random.default_rng(50)
+    for _ in range(100):
+        a, b = rng.uniform(-1, 1, 2)
+        f = orc.flux("burgers", [a], [b], 0)[0]
+        assert f == pytest.approx(orc.flux("burgers", [b], [a], 0)[0], rel=3e-16)
+        # entropy U = u^2/2, v = u, psi = u^3/6:  (b - a) f = (b^3 - a^3)/6
+        assert abs((b - a) * f - (b ** 3 - a ** 3) / 6) <= 4e-16 * (abs(a) + abs(b)) ** 3
+        assert orc.flux("burgers", [a], [a], 0)[0] == pytest.approx(a * a / 2, rel=1e-15)
+
+
+def test_product_flux(orc):
+    assert orc.flux("product", [3.0], [7.0], 1)[0] == 21.0
