@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Benchmark of the sum-factorized flux-differencing volume term on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step = one evaluation of y = sum_m (A_m o F_m) 1 (FP64, sum-factorized
+kernel) over the whole workload: 3D Euler, Chandrashekar flux, n = 8
+Gauss-Legendre nodes (p = 7), 32768 elements of which 3277 are free-stream,
+inputs resident in HBM before the timed region.  Prints ONE JSON line.
+
+Besides the headline FP64 number the line carries: the FP32-split form on
+the same workload (throughput and error against the CPU oracle), the dense
+O(n^(2d)) GPU path on a subset, the n = 4 workload timed as 100 launches in
+one captured HIP graph, the serving loop's latency (when built), the
+roofline of the dominant kernel and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DOF/s and elem-evals/s, 3D Euler p=7, FP64 vs FP32 split; p99 serve latency"
+
+# MI355X published peaks
+PEAK_FP64_TFLOPS = 78.6      # vector FP64 (an FMA counts 2 flops): 256 CU x 64 lanes x 2 x 2.4 GHz
+PEAK_FP64_LANE_OPS = 3.93e13  # FP64 VALU lane-operations per second (one per lane per cycle)
+PEAK_HBM_GBS = 8000.0
+
+# Modelled FP64 VALU lane-operations of the method (per unique pair flux
+# including its two Hadamard updates, and per diagonal physical flux).
+OPS_PER_PAIR = 65
+OPS_PER_DIAG = 25
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def model_ops_per_element(n: int, d: int = 3) -> int:
+    lines = d * n ** (d - 1)
+    return lines * (n * (n - 1) // 2) * OPS_PER_PAIR + d * n ** d * OPS_PER_DIAG
+
+
+def timed_launches(torch, fn, steps: int, stream):
+    """Run fn() `steps` times on `stream`; (total ms, mean per-launch ms)."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for k in range(steps):
+        evs[k][0].record(stream)
+        fn()
+        evs[k][1].record(stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    total = t0.elapsed_time(t1)
+    per = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    return total, per
+
+
+def normwise(y, ref):
+    out = []
+    for v in range(ref.shape[0]):
+        d = np.abs(y[v] - ref[v])
+        out.append((float(d.max() / max(np.abs(ref[v]).max(), 1e-300)),
+                    float(d.sum() / max(np.abs(ref[v]).sum(), 1e-300))))
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=256, help="elements in the CPU-oracle sample")
+    ap.add_argument("--no-extras", action="store_true", help="headline FP64 number only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(elements are independent, so the term shards by element range with no exchange, "
+              "but only the one-GPU kernel is built and measured)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2306_11665_amd import sfhad, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    props = torch.cuda.get_device_properties(0)
+    w = W.WORKLOADS["euler3d_n8_gl_e32768"]
+    log(f"[bench] device {props.name} ({getattr(props, 'gcnArchName', '?')}, {props.multi_processor_count} CUs); "
+        f"workload {w.name}")
+    u = w.state()
+    ut = torch.from_numpy(u).cuda()
+    out = torch.empty_like(ut)
+    stream = torch.cuda.Stream()
+    E, n = w.E, w.n
+    dof = w.dof
+
+    def step64():
+        sfhad.volume(ut, n, 3, "euler", out=out, stream=stream)
+
+    for _ in range(args.warmup):
+        step64()
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup}); timing {args.steps} FP64 steps")
+    total_ms, kern_ms = timed_launches(torch, step64, args.steps, stream)
+    ms_per_step = total_ms / args.steps
+    value = dof / (ms_per_step * 1e-3)
+    log(f"[bench] FP64: {ms_per_step:.4f} ms/step, {value:.4e} DOF/s")
+
+    ops = model_ops_per_element(n) * E
+    achieved_lane_ops = ops / (kern_ms * 1e-3)
+    bytes_per_launch = 2 * 5 * n ** 3 * 8 * E
+    roofline = {
+        "bound": "alu",
+        "achieved": round(2 * achieved_lane_ops / 1e12, 3),
+        "peak": PEAK_FP64_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved_lane_ops / PEAK_FP64_LANE_OPS, 4),
+        "traffic": None,
+        "kernel": "sf_volume_kernel<8,3,EulerFP64>",
+        "kernel_ms": round(kern_ms, 5),
+        "model_lane_ops_per_element": model_ops_per_element(n),
+        "hbm_algorithmic_GBps": round(bytes_per_launch / (kern_ms * 1e-3) / 1e9, 1),
+        "hbm_frac": round(bytes_per_launch / (kern_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+    }
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "flux": "euler-chandrashekar", "d": 3, "n": n, "p": n - 1,
+                   "nodes": "gauss-legendre", "elements": E, "freestream_elements": int(round(0.1 * E)),
+                   "precision": "fp64"},
+        "elem_evals_per_s": E / (ms_per_step * 1e-3),
+        "node_updates_per_s": E * n ** 3 / (ms_per_step * 1e-3),
+        "roofline": roofline,
+        "device": {"name": props.name, "arch": getattr(props, "gcnArchName", None),
+                   "cus": props.multi_processor_count},
+    }
+
+    if not args.no_extras:
+        # FP32-split form on the same workload
+        out32 = torch.empty_like(ut)
+
+        def step32():
+            sfhad.volume(ut, n, 3, "euler", out=out32, stream=stream, precision="fp32_split")
+
+        for _ in range(args.warmup):
+            step32()
+        t32, k32 = timed_launches(torch, step32, args.steps, stream)
+        ms32 = t32 / args.steps
+        result["fp32_split"] = {"value": dof / (ms32 * 1e-3), "unit": "DOF/s", "ms_per_step": ms32,
+                                "kernel_ms": k32, "speedup_vs_fp64": ms_per_step / ms32}
+        log(f"[bench] FP32-split: {ms32:.4f} ms/step ({ms_per_step / ms32:.2f}x FP64)")
+
+        # dense O(n^(2d)) GPU path on a 4096-element subset
+        Es = 4096
+        us = ut[:, :Es, :].contiguous()
+        outd = torch.empty_like(us)
+
+        def stepd():
+            sfhad.dense_volume(us, n, 3, "euler", out=outd, stream=stream)
+
+        stepd()
+        td, kd = timed_launches(torch, stepd, 2, stream)
+        msd = td / 2
+        ms_sf_per_elem = ms_per_step / E
+        result["dense"] = {"elements": Es, "ms": msd, "ms_per_element": msd / Es,
+                           "speedup_sf_vs_dense": (msd / Es) / ms_sf_per_elem,
+                           "flux_evals_per_element": 3 * (n ** 3) ** 2,
+                           "target_speedup": n ** 2 / 2}
+        log(f"[bench] dense: {msd:.2f} ms for {Es} elements -> sf is "
+            f"{(msd / Es) / ms_sf_per_elem:.1f}x faster per element")
+
+        # n = 4 workload: 100 launches captured in one HIP graph
+        w2 = W.WORKLOADS["euler3d_n4_gl_e4096"]
+        u2 = torch.from_numpy(w2.state()).cuda()
+        o2 = torch.empty_like(u2)
+        g = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        sfhad.volume(u2, 4, 3, "euler", out=o2, stream=cap)   # warm (operator cache, module load)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=cap):
+            for _ in range(100):
+                sfhad.volume(u2, 4, 3, "euler", out=o2, stream=cap)
+        g.replay()
+        torch.cuda.synchronize()
+        tg0 = torch.cuda.Event(enable_timing=True)
+        tg1 = torch.cuda.Event(enable_timing=True)
+        tg0.record()
+        for _ in range(3):
+            g.replay()
+        tg1.record()
+        torch.cuda.synchronize()
+        per_launch = tg0.elapsed_time(tg1) / 300
+        result["euler3d_n4_gl_e4096"] = {"ms_per_launch_graph": per_launch,
+                                         "dof_per_s": w2.dof / (per_launch * 1e-3),
+                                         "elem_evals_per_s": w2.E / (per_launch * 1e-3)}
+        log(f"[bench] n=4 E=4096 in a graph: {per_launch * 1e3:.2f} us/launch")
+
+    if not args.no_cpu:
+        import oracle
+        cores = oracle.num_threads()
+        fs = W.freestream_index(w)
+        k = args.cpu_sample
+        sample = W.sample_elements(E, k - k // 10, seed=77, must_include=fs[: k // 10].tolist())
+        us_np = np.ascontiguousarray(u[:, sample, :])
+        log(f"[bench] CPU oracle on {len(sample)} sampled elements with {cores} threads")
+        t0 = time.perf_counter()
+        ref = oracle.dense_volume(us_np, n, 3, "euler")
+        tc = time.perf_counter() - t0
+        Es_ = len(sample)
+        result["cpu_baseline"] = {
+            "value": Es_ * n ** 3 * 5 / tc, "unit": "DOF/s", "cores": cores, "kind": "oracle",
+            "sample": f"{Es_} of the {E} elements (seeded, {min(len(fs), k // 10)} free-stream), "
+                      f"dense O(n^(2d)) FP64 definition, {tc:.2f} s wall",
+            "elem_evals_per_s": Es_ / tc,
+        }
+        t0 = time.perf_counter()
+        ref_sf = oracle.sf_volume(us_np, n, 3, "euler")
+        tsf = time.perf_counter() - t0
+        result["cpu_sf_method"] = {"value": Es_ * n ** 3 * 5 / tsf, "unit": "DOF/s", "cores": cores,
+                                   "elem_evals_per_s": Es_ / tsf}
+        y64 = out.cpu().numpy()[:, sample, :]
+        err64 = normwise(y64, ref)
+        result["fp64_error_vs_oracle"] = {"max": max(e[0] for e in err64), "per_variable": err64}
+        if "fp32_split" in result:
+            y32 = out32.cpu().numpy()[:, sample, :]
+            err32 = normwise(y32, ref)
+            result["fp32_split"]["error_vs_oracle"] = {
+                "variables": ["rho", "rho_u", "rho_v", "rho_w", "E"],
+                "max": [e[0] for e in err32], "mean": [e[1] for e in err32]}
+        del ref_sf
+        log(f"[bench] oracle {tc:.2f} s; FP64 max normwise error {result['fp64_error_vs_oracle']['max']:.2e}")
+
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,183 @@
+/*
+ * sfhad.h -- C-ABI of the MI355X (gfx950) sum-factorized Hadamard-product
+ * library (libsfhad.so).
+ *
+ * The library evaluates the flux-differencing volume term of an
+ * entropy-conserving high-order scheme on a mesh of E independent hexahedral
+ * (d = 3) or quadrilateral (d = 2) elements:
+ *
+ *     y = sum_{m=0}^{d-1} (A_m o F_m) 1 ,    F_m[i][j] = f_m(u_i, u_j),
+ *
+ * where A_m is the Kronecker product with the dense 1D operator Q = W D in
+ * direction m and the diagonal weight matrix W = diag(w) in every other
+ * direction (Eq. (5) of Cicchino & Nadarajah, "Scalable Evaluation of
+ * Hadamard Products with Tensor Product Basis for Entropy-Stable High-Order
+ * Methods").  Because every factor but one is diagonal, only the d n^(d+1)
+ * node pairs that share a grid line carry nonzero coefficients (Eq. (3),
+ * Theorem 1); sf_hadamard_volume evaluates the two-point flux on exactly
+ * those pairs, dense_hadamard_volume on all n^(2d) pairs (Eq. (1), the
+ * direct form the paper's Figure 1 compares against).
+ *
+ * CONVENTIONS (all entry points)
+ *  - Pointers are DEVICE pointers unless the name ends in _host.  The caller
+ *    owns every buffer it passes; the library never frees caller memory.
+ *  - State and output layout (structure of arrays, FP64):
+ *        u[v * E * n^d + e * n^d + node],  node = ix + n*iy + n*n*iz
+ *    (x fastest, then y, then z: the ordering of Section 2).  v runs over
+ *    the conserved variables: 1 for the scalar fluxes, 5 for Euler in the
+ *    order (rho, rho*u, rho*v, rho*w, E).  `out` has the same layout.
+ *  - Nodes are on [-1, 1]; Q = diag(w) D with D the collocated Lagrange
+ *    derivative matrix; no factor 2 is applied to the Hadamard sum.
+ *  - Calls are asynchronous on the given HIP stream (the null stream for the
+ *    short forms).  Arguments are validated on the host before any HIP call.
+ *  - Errors are negative sf_status values; sf_last_error() returns a
+ *    thread-local detail string for the last failing call on that thread.
+ *  - Non-physical Euler states (rho <= 0 or p <= 0) are outside the domain:
+ *    the result is unspecified (NaN/Inf propagate) and nothing is checked on
+ *    the device.  The FP64 kernels assume rho, p in [1e-60, 1e60].
+ *  - Thread safety: the operator cache is mutex-protected; calls on distinct
+ *    streams are independent.
+ */
+#ifndef SFHAD_H
+#define SFHAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SF_OK = 0,
+    SF_ERR_ARG = -1,          /* null pointer, negative size, aliasing, bad enum */
+    SF_ERR_UNSUPPORTED = -2,  /* valid request outside the built shapes (n, d, flux, precision) */
+    SF_ERR_HIP = -3,          /* a HIP runtime call failed; detail in sf_last_error() */
+    SF_ERR_NOMEM = -4,        /* a device or host allocation failed */
+    SF_ERR_BUDGET = -5,       /* serving: the request can never fit the HBM budget */
+    SF_ERR_BUSY = -6,         /* serving: no free slot / budget right now (retry later) */
+    SF_ERR_NOT_FOUND = -7     /* serving: unknown mesh or ticket */
+} sf_status;
+
+typedef enum {
+    SF_FLUX_BURGERS_EC = 0,           /* f(a,b) = (a^2 + ab + b^2)/6, 1 variable */
+    SF_FLUX_EULER_CHANDRASHEKAR = 1,  /* Chandrashekar's EC/KEP flux, 5 variables, d = 3 */
+    SF_FLUX_PRODUCT = 2               /* f(a,b) = a b (C_ij = c_i c_j of the Results section) */
+} sf_flux_kind;
+
+typedef enum {
+    SF_NODES_GAUSS_LEGENDRE = 0,
+    SF_NODES_GAUSS_LOBATTO = 1
+} sf_node_kind;
+
+typedef enum {
+    SF_PREC_FP64 = 0,        /* FP64 throughout */
+    SF_PREC_FP32_SPLIT = 1   /* FP32 flux and line sums; FP64 near-equal log-means and direction sum */
+} sf_precision;
+
+/* Supported shapes:
+ *   d in {2, 3};  scalar fluxes: 2 <= n <= 16;  Euler: d = 3, 2 <= n <= 13;
+ *   dense_hadamard_volume additionally needs n^d <= 4096 and SF_PREC_FP64;
+ *   SF_PREC_FP32_SPLIT is built for the Euler flux only. */
+#define SF_MIN_N 2
+#define SF_MAX_N 16
+#define SF_MAX_N_EULER 13
+
+/* Optional arguments of the _ex entry points.  Initialise with
+ * sf_opts_init() and override fields as needed. */
+typedef struct sf_opts {
+    int node_kind;              /* sf_node_kind, default SF_NODES_GAUSS_LEGENDRE */
+    int precision;              /* sf_precision, default SF_PREC_FP64 */
+    double gamma;               /* ratio of specific heats, default 1.4 (Euler only) */
+    void *stream;               /* hipStream_t to launch on, default null stream */
+    const double *op_1d_host;   /* optional n x n row-major override of Q (host, copied) */
+    const double *w_1d_host;    /* optional n override of w (host, copied); both or neither */
+} sf_opts;
+
+/* Fill *opts with the defaults listed above.  Returns SF_ERR_ARG on NULL. */
+int sf_opts_init(sf_opts *opts);
+
+/* Sum-factorized volume term (Eq. (3) with the coefficients of Eq. (5);
+ * Algorithms 1-2 become index arithmetic inside the kernel).
+ *   u_nodes    device, n_var * E * n^d doubles, read only
+ *   elem_count E >= 0 (E = 0 is a successful no-op)
+ *   n          nodes per direction (polynomial degree + 1)
+ *   d          dimension, 2 or 3
+ *   flux_kind  sf_flux_kind
+ *   out        device, n_var * E * n^d doubles, fully overwritten; must not
+ *              overlap u_nodes
+ * Gauss-Legendre nodes, gamma = 1.4, FP64, null stream. */
+int sf_hadamard_volume(const double *u_nodes, int64_t elem_count, int n, int d,
+                       int flux_kind, double *out);
+
+/* Dense O(n^(2d)) evaluation of the same term (Eq. (1)/(3) taken literally:
+ * every A_m[i][j], zero or not, times f_m(u_i, u_j) for all i, j).  Same
+ * arguments and layout as sf_hadamard_volume.  The speed baseline. */
+int dense_hadamard_volume(const double *u_nodes, int64_t elem_count, int n, int d,
+                          int flux_kind, double *out);
+
+/* As above with options (opts may be NULL for the defaults). */
+int sf_hadamard_volume_ex(const double *u_nodes, int64_t elem_count, int n, int d,
+                          int flux_kind, double *out, const sf_opts *opts);
+int dense_hadamard_volume_ex(const double *u_nodes, int64_t elem_count, int n, int d,
+                             int flux_kind, double *out, const sf_opts *opts);
+
+/* The 1D operator the kernels use (FP64, on [-1, 1]): nodes x, weights w and
+ * Q = diag(w) D, row-major n x n (Eq. (5)).  Host buffers of n, n and n*n
+ * doubles; any of them may be NULL.  No GPU needed. */
+int sf_operator_1d(int n, int node_kind, double *x_host, double *w_host, double *Q_host);
+
+/* Select the HIP device for the calling thread and build the operators for
+ * every n up to n_max (optional warm-up; the first call per shape otherwise
+ * does it).  Returns SF_ERR_HIP when no device is usable. */
+int sf_init(int device, int n_max);
+
+/* Human-readable name of a status code (static storage). */
+const char *sf_status_string(int status);
+
+/* Detail of the last failing call on this thread ("" if none). */
+const char *sf_last_error(void);
+
+/* Library version string (static storage). */
+const char *sf_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of residual-evaluation requests over          */
+/* device-resident meshes of mixed n (one GPU).                               */
+/* ------------------------------------------------------------------------ */
+typedef struct sf_server sf_server;
+typedef int64_t sf_mesh;
+typedef int64_t sf_ticket;
+
+/* Create a server on the current device.  hbm_budget_bytes bounds the
+ * device memory held by in-flight request outputs; max_inflight bounds the
+ * number of requests resident on the device at once (1..1024). */
+int sf_server_create(size_t hbm_budget_bytes, int max_inflight, sf_server **out);
+
+/* Register a mesh: the state (layout as above, Euler, d = 3) is copied to a
+ * device buffer the server owns.  u_host points to host memory. */
+int sf_mesh_register(sf_server *srv, const double *u_host, int64_t elem_count, int n,
+                     int flux_kind, int node_kind, sf_mesh *out);
+
+/* Submit one residual evaluation of a registered mesh (non-blocking). */
+int sf_submit(sf_server *srv, sf_mesh mesh, int precision, sf_ticket *out);
+
+/* Non-blocking completion check: 1 if done, 0 if not, <0 on error. */
+int sf_poll(sf_server *srv, sf_ticket ticket);
+
+/* Block until the ticket completes; *y_dev points to the result (device,
+ * owned by the server until sf_release), *latency_s is submit-to-completion
+ * time on the host clock.  Either output pointer may be NULL. */
+int sf_wait(sf_server *srv, sf_ticket ticket, const double **y_dev, double *latency_s);
+
+/* Return a completed ticket's output buffer to the budget. */
+int sf_release(sf_server *srv, sf_ticket ticket);
+
+int sf_mesh_unregister(sf_server *srv, sf_mesh mesh);
+int sf_server_destroy(sf_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFHAD_H */

@@ -1,0 +1,187 @@
+// The C-ABI entry points: argument validation (all of it on the host, before
+// any HIP call), operator lookup, and dispatch to the kernel launchers.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "sfhad_internal.h"
+
+namespace sfhad {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+namespace {
+
+int fail(int status, const char *msg) {
+    set_error(msg);
+    return status;
+}
+
+int64_t ipow(int b, int e) {
+    int64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+// Shared validation of a volume-term request; fills `r` on success.
+int validate(const double *u, int64_t E, int n, int d, int flux, double *out, const sf_opts *opts,
+             bool dense, VolumeRequest &r) {
+    sf_opts o;
+    sf_opts_init(&o);
+    if (opts) o = *opts;
+    if (E < 0) return fail(SF_ERR_ARG, "elem_count must be >= 0");
+    if (n < 1) return fail(SF_ERR_ARG, "n must be >= 1");
+    if (d < 1) return fail(SF_ERR_ARG, "d must be >= 1");
+    const int nv = flux_nvar(flux);
+    if (nv == 0) return fail(SF_ERR_ARG, "unknown flux_kind");
+    if (o.node_kind != SF_NODES_GAUSS_LEGENDRE && o.node_kind != SF_NODES_GAUSS_LOBATTO)
+        return fail(SF_ERR_ARG, "unknown node_kind");
+    if (o.precision != SF_PREC_FP64 && o.precision != SF_PREC_FP32_SPLIT)
+        return fail(SF_ERR_ARG, "unknown precision");
+    if (!(o.gamma > 1.0) || !std::isfinite(o.gamma)) return fail(SF_ERR_ARG, "gamma must be finite and > 1");
+    if ((o.op_1d_host == nullptr) != (o.w_1d_host == nullptr))
+        return fail(SF_ERR_ARG, "op_1d_host and w_1d_host must be given together");
+    if (d > 3 || d == 1) return fail(SF_ERR_UNSUPPORTED, "d must be 2 or 3");
+    if (n < SF_MIN_N || n > SF_MAX_N) return fail(SF_ERR_UNSUPPORTED, "n outside [2, 16]");
+    if (flux == SF_FLUX_EULER_CHANDRASHEKAR) {
+        if (d != 3) return fail(SF_ERR_UNSUPPORTED, "the Euler flux is built for d = 3");
+        if (n > SF_MAX_N_EULER) return fail(SF_ERR_UNSUPPORTED, "the Euler flux is built for n <= 13");
+    }
+    if (o.precision == SF_PREC_FP32_SPLIT && flux != SF_FLUX_EULER_CHANDRASHEKAR)
+        return fail(SF_ERR_UNSUPPORTED, "the FP32-split form is built for the Euler flux only");
+    if (dense) {
+        if (ipow(n, d) > 4096) return fail(SF_ERR_UNSUPPORTED, "dense path needs n^d <= 4096");
+        if (o.precision != SF_PREC_FP64) return fail(SF_ERR_UNSUPPORTED, "dense path is FP64 only");
+    }
+    const int64_t N = ipow(n, d);
+    if (E > 0 && E > INT64_MAX / (N * nv)) return fail(SF_ERR_ARG, "elem_count too large");
+    r.E = E;
+    r.n = n;
+    r.d = d;
+    r.flux = flux;
+    r.precision = o.precision;
+    r.gamma = o.gamma;
+    r.stream = reinterpret_cast<hipStream_t>(o.stream);
+    r.u = u;
+    r.out = out;
+    if (E == 0) return SF_OK;
+    if (!u || !out) return fail(SF_ERR_ARG, "null u_nodes or out");
+    const size_t bytes = (size_t)(N * nv * E) * sizeof(double);
+    const char *ub = reinterpret_cast<const char *>(u), *ob = reinterpret_cast<const char *>(out);
+    if (ub < ob + bytes && ob < ub + bytes) return fail(SF_ERR_ARG, "out overlaps u_nodes");
+    if (o.op_1d_host) {
+        r.op.n = n;
+        r.op.node_kind = o.node_kind;
+        for (int i = 0; i < n * n; ++i) r.op.Q[i] = o.op_1d_host[i];
+        for (int i = 0; i < n; ++i) {
+            r.op.w[i] = o.w_1d_host[i];
+            r.op.x[i] = 0.0;
+        }
+    } else if (!get_operator(n, o.node_kind, r.op)) {
+        return fail(SF_ERR_UNSUPPORTED, "operator construction failed");
+    }
+    return SF_OK;
+}
+
+int run(const double *u, int64_t E, int n, int d, int flux, double *out, const sf_opts *opts,
+        bool dense) {
+    VolumeRequest r;
+    int st = validate(u, E, n, d, flux, out, opts, dense, r);
+    if (st != SF_OK || E == 0) return st;
+    return dense ? launch_dense_volume(r) : launch_sf_volume(r);
+}
+
+}  // namespace
+}  // namespace sfhad
+
+using namespace sfhad;
+
+extern "C" {
+
+int sf_opts_init(sf_opts *opts) {
+    if (!opts) return SF_ERR_ARG;
+    opts->node_kind = SF_NODES_GAUSS_LEGENDRE;
+    opts->precision = SF_PREC_FP64;
+    opts->gamma = 1.4;
+    opts->stream = nullptr;
+    opts->op_1d_host = nullptr;
+    opts->w_1d_host = nullptr;
+    return SF_OK;
+}
+
+int sf_hadamard_volume(const double *u, int64_t E, int n, int d, int flux, double *out) {
+    return run(u, E, n, d, flux, out, nullptr, false);
+}
+
+int dense_hadamard_volume(const double *u, int64_t E, int n, int d, int flux, double *out) {
+    return run(u, E, n, d, flux, out, nullptr, true);
+}
+
+int sf_hadamard_volume_ex(const double *u, int64_t E, int n, int d, int flux, double *out,
+                          const sf_opts *opts) {
+    return run(u, E, n, d, flux, out, opts, false);
+}
+
+int dense_hadamard_volume_ex(const double *u, int64_t E, int n, int d, int flux, double *out,
+                             const sf_opts *opts) {
+    return run(u, E, n, d, flux, out, opts, true);
+}
+
+int sf_operator_1d(int n, int node_kind, double *x, double *w, double *Q) {
+    if (n < 1) return fail(SF_ERR_ARG, "n must be >= 1");
+    if (node_kind != SF_NODES_GAUSS_LEGENDRE && node_kind != SF_NODES_GAUSS_LOBATTO)
+        return fail(SF_ERR_ARG, "unknown node_kind");
+    if (n < SF_MIN_N || n > SF_MAX_N) return fail(SF_ERR_UNSUPPORTED, "n outside [2, 16]");
+    Operator1D op;
+    if (!get_operator(n, node_kind, op)) return fail(SF_ERR_UNSUPPORTED, "operator construction failed");
+    if (x) std::memcpy(x, op.x, sizeof(double) * n);
+    if (w) std::memcpy(w, op.w, sizeof(double) * n);
+    if (Q) std::memcpy(Q, op.Q, sizeof(double) * n * n);
+    return SF_OK;
+}
+
+int sf_init(int device, int n_max) {
+    int count = 0;
+    hipError_t err = hipGetDeviceCount(&count);
+    if (err != hipSuccess || count == 0) {
+        set_error(std::string("no HIP device: ") + (err != hipSuccess ? hipGetErrorString(err) : "count = 0"));
+        return SF_ERR_HIP;
+    }
+    if (device < 0 || device >= count) return fail(SF_ERR_ARG, "device index out of range");
+    err = hipSetDevice(device);
+    if (err != hipSuccess) {
+        set_error(std::string("hipSetDevice: ") + hipGetErrorString(err));
+        return SF_ERR_HIP;
+    }
+    if (n_max > SF_MAX_N) n_max = SF_MAX_N;
+    Operator1D op;
+    for (int n = SF_MIN_N; n <= n_max; ++n) {
+        get_operator(n, SF_NODES_GAUSS_LEGENDRE, op);
+        get_operator(n, SF_NODES_GAUSS_LOBATTO, op);
+    }
+    return SF_OK;
+}
+
+const char *sf_status_string(int status) {
+    switch (status) {
+        case SF_OK: return "SF_OK";
+        case SF_ERR_ARG: return "SF_ERR_ARG";
+        case SF_ERR_UNSUPPORTED: return "SF_ERR_UNSUPPORTED";
+        case SF_ERR_HIP: return "SF_ERR_HIP";
+        case SF_ERR_NOMEM: return "SF_ERR_NOMEM";
+        case SF_ERR_BUDGET: return "SF_ERR_BUDGET";
+        case SF_ERR_BUSY: return "SF_ERR_BUSY";
+        case SF_ERR_NOT_FOUND: return "SF_ERR_NOT_FOUND";
+        default: return "SF_UNKNOWN_STATUS";
+    }
+}
+
+const char *sf_last_error(void) { return g_last_error.c_str(); }
+
+const char *sf_version(void) { return "sfhad 0.1.0 (gfx950)"; }
+
+}  // extern "C"

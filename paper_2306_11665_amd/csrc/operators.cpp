@@ -1,0 +1,161 @@
+// Host construction of the 1D operators used by the kernels: nodes x and
+// weights w of the Gauss-Legendre or Gauss-Lobatto rule on [-1, 1], the
+// collocated Lagrange derivative D and Q = diag(w) D (the weighted 1D factor
+// of Eq. (5)).  Built once per (n, node kind) in FP64 and cached.
+//
+// Gauss-Legendre nodes: Newton on P_n from Tricomi's asymptotic guesses, with
+// P_n' from the recurrence P'_{k+1} = (k+1) P_k + x P'_k; weights
+// w = 2 / ((1 - x)(1 + x) P_n'(x)^2).
+// Gauss-Lobatto nodes: the roots of g = P_{N+1} - P_{N-1} (N = n - 1), which
+// are +-1 and the roots of P_N'; Newton uses g' = (2N + 1) P_N.  Weights
+// w = 2 / (N (N+1) P_N(x)^2).
+// D: off-diagonal entries from the Lagrange product formula
+// D_ij = prod_{k != i,j} (x_i - x_k) / prod_{k != j} (x_j - x_k); the
+// diagonal is minus the off-diagonal row sum, so that D 1 = 0 to rounding
+// (a constant state then gives a zero volume term).
+#include "sfhad_internal.h"
+
+#include <cmath>
+#include <mutex>
+#include <vector>
+
+namespace sfhad {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// P_k(x) for k = n and n - 1 via the three-term recurrence.
+void legendre_pair(int n, double x, double &pn, double &pnm1) {
+    double a = 1.0, b = x;  // P_0, P_1
+    if (n == 0) { pn = 1.0; pnm1 = 0.0; return; }
+    for (int k = 1; k < n; ++k) {
+        double c = ((2 * k + 1) * x * b - k * a) / (k + 1);
+        a = b;
+        b = c;
+    }
+    pn = b;
+    pnm1 = a;
+}
+
+// P_n(x) and P_n'(x), with P'_{k+1} = (k+1) P_k + x P'_k.
+void legendre_with_derivative(int n, double x, double &p, double &dp) {
+    double a = 1.0, b = x, db = 1.0;
+    if (n == 0) { p = 1.0; dp = 0.0; return; }
+    for (int k = 1; k < n; ++k) {
+        double c = ((2 * k + 1) * x * b - k * a) / (k + 1);
+        double dc = (k + 1) * b + x * db;
+        a = b;
+        b = c;
+        db = dc;
+    }
+    p = b;
+    dp = db;
+}
+
+double legendre_p(int n, double x) {
+    double pn, pm;
+    legendre_pair(n, x, pn, pm);
+    return pn;
+}
+
+void gauss_legendre(int n, double *x, double *w) {
+    for (int k = 1; k <= n; ++k) {
+        // Tricomi: x_k ~ (1 - 1/(8n^2) + 1/(8n^3)) cos(pi (4k - 1) / (4n + 2)), descending in k
+        double t = (1.0 - 1.0 / (8.0 * n * n) + 1.0 / (8.0 * n * n * n)) *
+                   std::cos(kPi * (4.0 * k - 1.0) / (4.0 * n + 2.0));
+        for (int it = 0; it < 60; ++it) {
+            double pn, dp;
+            legendre_with_derivative(n, t, pn, dp);
+            double dt = pn / dp;
+            t -= dt;
+            if (std::fabs(dt) <= 1e-17) break;
+        }
+        double pn, dp;
+        legendre_with_derivative(n, t, pn, dp);
+        int i = n - k;  // ascending order
+        x[i] = t;
+        w[i] = 2.0 / ((1.0 - t) * (1.0 + t) * dp * dp);
+    }
+    if (n % 2 == 1) x[n / 2] = 0.0;  // the middle root is exactly zero
+}
+
+void gauss_lobatto(int n, double *x, double *w) {
+    int N = n - 1;
+    x[0] = -1.0;
+    x[N] = 1.0;
+    for (int i = 1; i < N; ++i) {
+        double t = -std::cos(kPi * i / N);
+        for (int it = 0; it < 60; ++it) {
+            double g = legendre_p(N + 1, t) - legendre_p(N - 1, t);
+            double dg = (2.0 * N + 1.0) * legendre_p(N, t);
+            double dt = g / dg;
+            t -= dt;
+            if (std::fabs(dt) <= 1e-17) break;
+        }
+        x[i] = t;
+    }
+    if (n % 2 == 1) x[N / 2] = 0.0;
+    for (int i = 0; i <= N; ++i) {
+        double p = legendre_p(N, x[i]);
+        w[i] = 2.0 / (N * (N + 1.0) * p * p);
+    }
+}
+
+void derivative_matrix(int n, const double *x, double *D) {
+    for (int j = 0; j < n; ++j) {
+        double den = 1.0;
+        for (int k = 0; k < n; ++k)
+            if (k != j) den *= x[j] - x[k];
+        for (int i = 0; i < n; ++i) {
+            if (i == j) continue;
+            double num = 1.0;
+            for (int k = 0; k < n; ++k)
+                if (k != i && k != j) num *= x[i] - x[k];
+            D[i * n + j] = num / den;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j)
+            if (j != i) s += D[i * n + j];
+        D[i * n + i] = -s;
+    }
+}
+
+std::mutex g_mu;
+std::vector<Operator1D> g_cache[2];  // index by node kind, then n
+
+}  // namespace
+
+bool build_operator(int n, int node_kind, Operator1D &op) {
+    if (n < 1 || n > kMaxN) return false;
+    if (node_kind != SF_NODES_GAUSS_LEGENDRE && node_kind != SF_NODES_GAUSS_LOBATTO) return false;
+    if (node_kind == SF_NODES_GAUSS_LOBATTO && n < 2) return false;
+    op.n = n;
+    op.node_kind = node_kind;
+    if (node_kind == SF_NODES_GAUSS_LEGENDRE)
+        gauss_legendre(n, op.x, op.w);
+    else
+        gauss_lobatto(n, op.x, op.w);
+    double D[kMaxN * kMaxN];
+    derivative_matrix(n, op.x, D);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) op.Q[i * n + j] = op.w[i] * D[i * n + j];
+    return true;
+}
+
+bool get_operator(int n, int node_kind, Operator1D &op) {
+    if (node_kind != SF_NODES_GAUSS_LEGENDRE && node_kind != SF_NODES_GAUSS_LOBATTO) return false;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto &cache = g_cache[node_kind];
+    if (cache.empty()) cache.resize(kMaxN + 1);
+    if (n < 1 || n > kMaxN) return false;
+    if (cache[n].n != n) {
+        if (!build_operator(n, node_kind, cache[n])) return false;
+    }
+    op = cache[n];
+    return true;
+}
+
+}  // namespace sfhad

@@ -1,0 +1,60 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/sfhad.h"
+
+namespace sfhad {
+
+constexpr int kMaxN = 16;
+
+// The 1D operator of Eq. (5): nodes, weights and Q = diag(w) D (row-major).
+struct Operator1D {
+    int n = 0;
+    int node_kind = -1;
+    double x[kMaxN];
+    double w[kMaxN];
+    double Q[kMaxN * kMaxN];
+};
+
+bool build_operator(int n, int node_kind, Operator1D &op);
+bool get_operator(int n, int node_kind, Operator1D &op);
+
+// Thread-local error detail for sf_last_error().
+void set_error(const std::string &msg);
+
+// A fully validated volume-term request.
+struct VolumeRequest {
+    const double *u = nullptr;
+    double *out = nullptr;
+    int64_t E = 0;
+    int n = 0;
+    int d = 0;
+    int flux = 0;
+    int precision = SF_PREC_FP64;
+    double gamma = 1.4;
+    hipStream_t stream = nullptr;
+    Operator1D op;
+};
+
+// Kernel launchers (volume_kernels.hip / dense_kernels.hip).  They return
+// SF_OK, SF_ERR_UNSUPPORTED for a shape that is not instantiated, or
+// SF_ERR_HIP when the launch fails.
+int launch_sf_volume(const VolumeRequest &r);
+int launch_dense_volume(const VolumeRequest &r);
+
+// Number of conserved variables of a flux kind (0 for an unknown kind).
+inline int flux_nvar(int flux) {
+    switch (flux) {
+        case SF_FLUX_BURGERS_EC: return 1;
+        case SF_FLUX_PRODUCT: return 1;
+        case SF_FLUX_EULER_CHANDRASHEKAR: return 5;
+        default: return 0;
+    }
+}
+
+}  // namespace sfhad

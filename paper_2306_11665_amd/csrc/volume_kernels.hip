@@ -1,0 +1,216 @@
+// Sum-factorized volume kernels (Eq. (3) with the coefficients of Eq. (5)).
+//
+// One workgroup per block of EPB elements; d groups of LPD lanes, group m
+// handling every line of direction m of the block's elements, one line per
+// lane (at n = 8 in 3D: one element, 3 waves of 64 lanes, 64 lines each).
+//
+//   a1  stage:   coalesced SoA loads of the conserved state, conversion to
+//                the flux's per-node quantities, stored in LDS;
+//   a2  lines:   the lane's line = padded LDS base + a * stride (Algorithm 1
+//                as index arithmetic, nothing materialized);
+//   a3  coeffs:  Q[a][c] from the kernel arguments (scalar registers),
+//                w_perp once per line (Algorithm 2's values, on the fly);
+//   a4  flux:    every unordered pair (a < c) once plus the n diagonal
+//                physical fluxes;
+//   a5  reduce:  t_a += Q[a][c] F, t_c += Q[c][a] F in registers;
+//   a6  sum:     t * w_perp summed over the d directions in FP64 in LDS in the
+//                fixed order m = 0, 1, 2 (bit-reproducible), then coalesced
+//                stores.
+//   a7  the FP32-split form is the same kernel with the EulerFP32Split policy
+//                (FP32 inputs, flux and line sums; FP64 direction sum).
+#include "kernels_common.h"
+#include "sfhad_internal.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace sfhad {
+namespace dev {
+
+// LDS doubles per element array slot: the staged inputs (NS values of type
+// Real) and, after the compute phase, the FP64 outputs (NV values) share it.
+template <class P>
+constexpr int lds_words() {
+    constexpr int in_bytes = P::NS * (int)sizeof(typename P::Real);
+    constexpr int out_bytes = P::NV * 8;
+    return ((in_bytes > out_bytes ? in_bytes : out_bytes) + 7) / 8;
+}
+
+template <int N, int DIM, class P>
+__global__ void __launch_bounds__((Geom<N, DIM>::THREADS))
+sf_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int64_t E,
+                 const OpArg<N> op, double gamma) {
+    using G = Geom<N, DIM>;
+    using R = typename P::Real;
+    constexpr int AS = G::EPB * G::PADN;  // distance between two stored arrays (elements)
+    __shared__ double lds[lds_words<P>() * AS];
+    R *lin = reinterpret_cast<R *>(lds);  // staged inputs: NS arrays of type R
+    double *lout = lds;                   // outputs: NV arrays of doubles
+
+    const int tid = threadIdx.x;
+    const int64_t e0 = (int64_t)blockIdx.x * G::EPB;
+    const int nel = (int)((E - e0) < G::EPB ? (E - e0) : G::EPB);
+    const int nvalid = nel * G::NODES;
+    const size_t vstride = (size_t)E * G::NODES;
+    const size_t gbase = (size_t)e0 * G::NODES;
+
+    // a1: stage the block's nodes.
+    for (int i = tid; i < nvalid; i += G::THREADS) {
+        double uc[P::NV];
+        R s[P::NS];
+#pragma unroll
+        for (int v = 0; v < P::NV; ++v) uc[v] = u[v * vstride + gbase + i];
+        P::stage(uc, gamma, s);
+        const int el = i / G::NODES, node = i - el * G::NODES;
+        const int li = el * G::PADN + G::pidx(node);
+#pragma unroll
+        for (int k = 0; k < P::NS; ++k) lin[k * AS + li] = s[k];
+    }
+    __syncthreads();
+
+    // a2..a5: one line per lane.
+    const int m = tid / G::LPD;
+    const int r = tid - m * G::LPD;
+    const int el = r / G::LINES;
+    const int line = r - el * G::LINES;
+    const bool active = el < nel;
+    int pbase, pstride, q0, q1;
+    line_geometry<N, DIM>(m, line, pbase, pstride, q0, q1);
+    const double wperp = DIM == 3 ? op.w[q0] * op.w[q1] : op.w[q0];
+    const R cg = (R)(0.5 / (gamma - 1.0));
+    const R *le = lin + el * G::PADN;
+
+    R t[N][P::NV];
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+        for (int k = 0; k < P::NV; ++k) t[a][k] = (R)0;
+
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            const typename P::Node A = P::load(le, AS, pin(pbase + a * pstride), m);
+            R F[P::NV];
+            P::diag(A, gamma, F);
+            const R qaa = (R)op.Q[a * N + a];
+#pragma unroll
+            for (int k = 0; k < P::NV; ++k) t[a][k] = qaa * F[k] + t[a][k];
+#pragma unroll
+            for (int c = a + 1; c < N; ++c) {
+                // re-read node c from LDS for every pair: an opaque index stops
+                // the compiler from keeping the whole line live in registers
+                const typename P::Node C = P::load(le, AS, pin(pbase + c * pstride), m);
+                P::pair(A, C, cg, F);
+                const R qac = (R)op.Q[a * N + c], qca = (R)op.Q[c * N + a];
+#pragma unroll
+                for (int k = 0; k < P::NV; ++k) {
+                    t[a][k] = qac * F[k] + t[a][k];
+                    t[c][k] = qca * F[k] + t[c][k];
+                }
+                // one pair in flight at a time: its sums complete here, before
+                // the next pair's loads (ordered after this fence) are issued
+#pragma unroll
+                for (int k = 0; k < P::NV; ++k) {
+                    t[a][k] = pin(t[a][k]);
+                    t[c][k] = pin(t[c][k]);
+                }
+            }
+        }
+    }
+    __syncthreads();  // every lane is done reading the staged inputs
+
+    // a6: FP64 direction sum in LDS (the output arrays reuse the input space).
+    double *lo = lout + el * G::PADN;
+#pragma unroll
+    for (int mm = 0; mm < DIM; ++mm) {
+        if (m == mm && active) {
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                const int idx = pbase + a * pstride;
+#pragma unroll
+                for (int k = 0; k < P::NV; ++k) {
+                    double *dst = lo + P::out_array(k, m) * AS + idx;
+                    const double val = (double)t[a][k] * wperp;
+                    *dst = mm == 0 ? val : *dst + val;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int i = tid; i < nvalid; i += G::THREADS) {
+        const int e = i / G::NODES, node = i - e * G::NODES;
+        const int li = e * G::PADN + G::pidx(node);
+#pragma unroll
+        for (int v = 0; v < P::NV; ++v) out[v * vstride + gbase + i] = lout[v * AS + li];
+    }
+}
+
+template <int N>
+OpArg<N> make_op(const Operator1D &op) {
+    OpArg<N> a;
+    for (int i = 0; i < N * N; ++i) a.Q[i] = op.Q[i];
+    for (int i = 0; i < N; ++i) a.w[i] = op.w[i];
+    return a;
+}
+
+template <int N, int DIM, class P>
+int launch_sf(const VolumeRequest &r) {
+    using G = Geom<N, DIM>;
+    const int64_t blocks = (r.E + G::EPB - 1) / G::EPB;
+    if (blocks > 0x7fffffffLL) {
+        set_error("element count too large for one launch");
+        return SF_ERR_UNSUPPORTED;
+    }
+    hipLaunchKernelGGL((sf_volume_kernel<N, DIM, P>), dim3((unsigned)blocks), dim3(G::THREADS), 0,
+                       r.stream, r.u, r.out, r.E, make_op<N>(r.op), r.gamma);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) {
+        set_error(std::string("sf_volume_kernel launch: ") + hipGetErrorString(err));
+        return SF_ERR_HIP;
+    }
+    return SF_OK;
+}
+
+// Dispatch on n for a fixed (DIM, policy); n range [2, NMAX].
+template <int DIM, class P, int NMAX>
+int dispatch_n(const VolumeRequest &r) {
+    switch (r.n) {
+#define SF_CASE(NV_)                                                       \
+    case NV_:                                                              \
+        if constexpr (NV_ <= NMAX) return launch_sf<NV_, DIM, P>(r);       \
+        break;
+        SF_CASE(2) SF_CASE(3) SF_CASE(4) SF_CASE(5) SF_CASE(6) SF_CASE(7) SF_CASE(8) SF_CASE(9)
+        SF_CASE(10) SF_CASE(11) SF_CASE(12) SF_CASE(13) SF_CASE(14) SF_CASE(15) SF_CASE(16)
+#undef SF_CASE
+        default: break;
+    }
+    set_error("n outside the built range");
+    return SF_ERR_UNSUPPORTED;
+}
+
+}  // namespace dev
+
+int launch_sf_volume(const VolumeRequest &r) {
+    using namespace dev;
+    if (r.precision == SF_PREC_FP32_SPLIT) {
+        if (r.flux == SF_FLUX_EULER_CHANDRASHEKAR && r.d == 3)
+            return dispatch_n<3, EulerFP32Split, SF_MAX_N_EULER>(r);
+        set_error("the FP32-split form is built for the 3D Euler flux only");
+        return SF_ERR_UNSUPPORTED;
+    }
+    switch (r.flux) {
+        case SF_FLUX_BURGERS_EC:
+            return r.d == 2 ? dispatch_n<2, ScalarFlux<0>, 16>(r) : dispatch_n<3, ScalarFlux<0>, 16>(r);
+        case SF_FLUX_PRODUCT:
+            return r.d == 2 ? dispatch_n<2, ScalarFlux<2>, 16>(r) : dispatch_n<3, ScalarFlux<2>, 16>(r);
+        case SF_FLUX_EULER_CHANDRASHEKAR:
+            if (r.d != 3) break;
+            return dispatch_n<3, EulerFP64, SF_MAX_N_EULER>(r);
+        default: break;
+    }
+    set_error("flux / dimension combination not built");
+    return SF_ERR_UNSUPPORTED;
+}
+
+}  // namespace sfhad

@@ -1,0 +1,173 @@
+"""Thin ctypes binding of libsfhad.so (C-ABI in include/sfhad.h).
+
+Argument marshalling only: every step of the volume term runs in the HIP
+library.  PyTorch provides device memory and the stream; tensors must be
+contiguous float64 CUDA tensors in the layout u[v, e, node].  If the library
+is not built, every call raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsfhad.so")
+
+FLUX = {"burgers": 0, "euler": 1, "product": 2}
+NODES = {"gl": 0, "gll": 1}
+PRECISION = {"fp64": 0, "fp32_split": 1}
+NVAR = {"burgers": 1, "euler": 5, "product": 1}
+STATUS = {0: "SF_OK", -1: "SF_ERR_ARG", -2: "SF_ERR_UNSUPPORTED", -3: "SF_ERR_HIP",
+          -4: "SF_ERR_NOMEM", -5: "SF_ERR_BUDGET", -6: "SF_ERR_BUSY", -7: "SF_ERR_NOT_FOUND"}
+
+
+class SFError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}" + (f" ({detail})" if detail else ""))
+
+
+class SfOpts(ctypes.Structure):
+    _fields_ = [("node_kind", ctypes.c_int), ("precision", ctypes.c_int), ("gamma", ctypes.c_double),
+                ("stream", ctypes.c_void_p), ("op_1d_host", ctypes.POINTER(ctypes.c_double)),
+                ("w_1d_host", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def lib() -> ctypes.CDLL:
+    """Open libsfhad.so once (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2306_11665_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, ci, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+        for name in ("sf_hadamard_volume", "dense_hadamard_volume"):
+            f = getattr(L, name)
+            f.argtypes = [vp, i64, ci, ci, ci, vp]
+            f.restype = ci
+        for name in ("sf_hadamard_volume_ex", "dense_hadamard_volume_ex"):
+            f = getattr(L, name)
+            f.argtypes = [vp, i64, ci, ci, ci, vp, ctypes.POINTER(SfOpts)]
+            f.restype = ci
+        L.sf_opts_init.argtypes = [ctypes.POINTER(SfOpts)]
+        L.sf_opts_init.restype = ci
+        L.sf_operator_1d.argtypes = [ci, ci, _dp, _dp, _dp]
+        L.sf_operator_1d.restype = ci
+        L.sf_init.argtypes = [ci, ci]
+        L.sf_init.restype = ci
+        L.sf_status_string.argtypes = [ci]
+        L.sf_status_string.restype = ctypes.c_char_p
+        L.sf_last_error.argtypes = []
+        L.sf_last_error.restype = ctypes.c_char_p
+        L.sf_version.argtypes = []
+        L.sf_version.restype = ctypes.c_char_p
+        vpp = ctypes.POINTER(ctypes.c_void_p)
+        L.sf_server_create.argtypes = [ctypes.c_size_t, ci, vpp]
+        L.sf_server_create.restype = ci
+        L.sf_mesh_register.argtypes = [vp, _dp, i64, ci, ci, ci, ctypes.POINTER(i64)]
+        L.sf_mesh_register.restype = ci
+        L.sf_submit.argtypes = [vp, i64, ci, ctypes.POINTER(i64)]
+        L.sf_submit.restype = ci
+        L.sf_poll.argtypes = [vp, i64]
+        L.sf_poll.restype = ci
+        L.sf_wait.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double)]
+        L.sf_wait.restype = ci
+        for name in ("sf_release", "sf_mesh_unregister"):
+            getattr(L, name).argtypes = [vp, i64]
+            getattr(L, name).restype = ci
+        L.sf_server_destroy.argtypes = [vp]
+        L.sf_server_destroy.restype = ci
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().sf_last_error().decode()
+
+
+def check(status: int, where: str) -> int:
+    if status < 0:
+        raise SFError(status, where, last_error())
+    return status
+
+
+def operator_1d(n: int, nodes: str = "gl"):
+    """(x, w, Q) of the library's 1D operator, Q = diag(w) D (host, FP64)."""
+    x = np.zeros(n); w = np.zeros(n); Q = np.zeros((n, n))
+    check(lib().sf_operator_1d(n, NODES[nodes], x.ctypes.data_as(_dp), w.ctypes.data_as(_dp),
+                               Q.ctypes.data_as(_dp)), "sf_operator_1d")
+    return x, w, Q
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def make_opts(nodes="gl", precision="fp64", gamma=1.4, stream=None, Q=None, w=None):
+    o = SfOpts()
+    lib().sf_opts_init(ctypes.byref(o))
+    o.node_kind = NODES[nodes]
+    o.precision = PRECISION[precision]
+    o.gamma = float(gamma)
+    o.stream = _stream_handle(stream)
+    keep = []
+    if Q is not None or w is not None:
+        Qh = np.ascontiguousarray(Q, dtype=np.float64)
+        wh = np.ascontiguousarray(w, dtype=np.float64)
+        keep = [Qh, wh]
+        o.op_1d_host = Qh.ctypes.data_as(_dp)
+        o.w_1d_host = wh.ctypes.data_as(_dp)
+    return o, keep
+
+
+def _check_tensor(u, flux: str, n: int, d: int):
+    import torch
+    nv = NVAR[flux]
+    if not isinstance(u, torch.Tensor) or u.device.type != "cuda" or u.dtype != torch.float64:
+        raise TypeError("u must be a float64 CUDA tensor")
+    if not u.is_contiguous() or u.dim() != 3 or u.shape[0] != nv or u.shape[2] != n ** d:
+        raise ValueError(f"u must be a contiguous ({nv}, E, {n ** d}) tensor, got {tuple(u.shape)}")
+
+
+def _call(fn_name: str, u, n: int, d: int, flux: str, *, nodes="gl", precision="fp64", gamma=1.4,
+          stream=None, out=None, Q=None, w=None):
+    import torch
+    _check_tensor(u, flux, n, d)
+    if out is None:
+        out = torch.empty_like(u)
+    else:
+        _check_tensor(out, flux, n, d)
+    opts, keep = make_opts(nodes, precision, gamma, stream, Q, w)
+    fn = getattr(lib(), fn_name)
+    check(fn(u.data_ptr(), u.shape[1], n, d, FLUX[flux], out.data_ptr(), ctypes.byref(opts)), fn_name)
+    del keep
+    return out
+
+
+def volume(u, n: int, d: int, flux: str, **kw):
+    """y = sum_m (A_m o F_m) 1 by the sum-factorized kernels (sf_hadamard_volume_ex)."""
+    return _call("sf_hadamard_volume_ex", u, n, d, flux, **kw)
+
+
+def dense_volume(u, n: int, d: int, flux: str, **kw):
+    """Same term over all n^(2d) pairs (dense_hadamard_volume_ex)."""
+    return _call("dense_hadamard_volume_ex", u, n, d, flux, **kw)
+
+
+def volume_raw(u_ptr: int, E: int, n: int, d: int, flux: int, out_ptr: int) -> int:
+    """The short C entry point with raw device pointers (returns the status)."""
+    return lib().sf_hadamard_volume(u_ptr, E, n, d, flux, out_ptr)
+
+
+def dense_volume_raw(u_ptr: int, E: int, n: int, d: int, flux: int, out_ptr: int) -> int:
+    return lib().dense_hadamard_volume(u_ptr, E, n, d, flux, out_ptr)

@@ -1,0 +1,134 @@
+"""Host-side tests of the C-ABI library (no GPU needed, no kernel launched).
+
+The library must load, export every function include/sfhad.h declares, build
+its 1D operators on the host (checked against the oracle's), and reject
+every malformed request before any HIP call.  Pointer arguments below are
+either NULL or deliberately invalid host addresses that validation must
+reject; no case here reaches a launch.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sfhad.h")
+
+
+@pytest.fixture(scope="module")
+def sf():
+    from paper_2306_11665_amd import sfhad
+    if not os.path.exists(sfhad.LIB_PATH):
+        pytest.fail("libsfhad.so is not built (run __graft_entry__.build())")
+    sfhad.lib()
+    return sfhad
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", txt, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while", "for", "return")))
+
+
+def test_every_declared_symbol_is_exported(sf):
+    names = declared_functions()
+    assert "sf_hadamard_volume" in names and "dense_hadamard_volume" in names
+    assert len(names) >= 18, names
+    L = sf.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings(sf):
+    L = sf.lib()
+    for code, name in sf.STATUS.items():
+        assert L.sf_status_string(code).decode() == name
+    assert L.sf_status_string(12345).decode() == "SF_UNKNOWN_STATUS"
+    assert L.sf_version().decode().startswith("sfhad")
+
+
+@pytest.mark.parametrize("kind", ["gl", "gll"])
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 8, 12, 16])
+def test_operator_matches_oracle(sf, orc, n, kind):
+    x, w, Q = sf.operator_1d(n, kind)
+    xo, wo, Do, Qo = orc.operator_1d(n, kind)
+    np.testing.assert_allclose(x, xo, rtol=0, atol=4e-16)
+    np.testing.assert_allclose(w, wo, rtol=5e-15)
+    assert np.abs(Q - Qo).max() <= 2e-14 * np.abs(Qo).max()
+    assert np.abs(Q.sum(axis=1)).max() <= 4e-15 * np.abs(Q).max()   # Q 1 = 0
+
+
+def test_operator_bad_args(sf):
+    L = sf.lib()
+    assert L.sf_operator_1d(0, 0, None, None, None) == -1
+    assert L.sf_operator_1d(4, 7, None, None, None) == -1
+    assert L.sf_operator_1d(17, 0, None, None, None) == -2
+    assert L.sf_operator_1d(1, 0, None, None, None) == -2
+    assert L.sf_operator_1d(4, 0, None, None, None) == 0     # outputs optional
+
+
+BAD = 0x1000  # an address validation must reject before it is ever used
+
+
+@pytest.mark.parametrize("fn", ["sf_hadamard_volume", "dense_hadamard_volume"])
+def test_validation_errors(sf, fn):
+    L = sf.lib()
+    f = getattr(L, fn)
+    assert f(None, 4, 4, 3, 1, None) == -1               # null pointers
+    assert "null" in sf.last_error()
+    assert f(BAD, -1, 4, 3, 1, BAD + 10 ** 9) == -1       # negative E
+    assert f(BAD, 4, 0, 3, 1, BAD + 10 ** 9) == -1        # n < 1
+    assert f(BAD, 4, 4, 0, 1, BAD + 10 ** 9) == -1        # d < 1
+    assert f(BAD, 4, 4, 3, 9, BAD + 10 ** 9) == -1        # unknown flux
+    assert f(BAD, 4, 1, 3, 0, BAD + 10 ** 9) == -2        # n = 1 not built
+    assert f(BAD, 4, 17, 2, 0, BAD + 10 ** 9) == -2       # n > 16
+    assert f(BAD, 4, 4, 1, 0, BAD + 10 ** 9) == -2        # d = 1
+    assert f(BAD, 4, 4, 4, 0, BAD + 10 ** 9) == -2        # d = 4
+    assert f(BAD, 4, 4, 2, 1, BAD + 10 ** 9) == -2        # Euler needs d = 3
+    assert f(BAD, 4, 14, 3, 1, BAD + 10 ** 9) == -2       # Euler n <= 13
+    assert f(BAD, 4, 4, 3, 1, BAD) == -1                  # out aliases u
+    assert f(BAD, 4, 4, 3, 1, BAD + 100) == -1            # out overlaps u
+    assert f(None, 0, 4, 3, 1, None) == 0                 # E = 0: no-op
+
+
+def test_opts_validation(sf):
+    L = sf.lib()
+    o = sf.SfOpts()
+    assert L.sf_opts_init(ctypes.byref(o)) == 0
+    assert (o.node_kind, o.precision, o.gamma) == (0, 0, 1.4)
+    assert L.sf_opts_init(None) == -1
+
+    def call(opts, flux=1, fn="sf_hadamard_volume_ex"):
+        return getattr(L, fn)(BAD, 4, 4, 3, flux, BAD, ctypes.byref(opts))
+
+    bad = sf.SfOpts(); L.sf_opts_init(ctypes.byref(bad)); bad.node_kind = 5
+    assert call(bad) == -1
+    bad = sf.SfOpts(); L.sf_opts_init(ctypes.byref(bad)); bad.precision = 3
+    assert call(bad) == -1
+    bad = sf.SfOpts(); L.sf_opts_init(ctypes.byref(bad)); bad.gamma = 1.0
+    assert call(bad) == -1
+    bad = sf.SfOpts(); L.sf_opts_init(ctypes.byref(bad)); bad.gamma = float("nan")
+    assert call(bad) == -1
+    Q = np.zeros(16)
+    bad = sf.SfOpts(); L.sf_opts_init(ctypes.byref(bad))
+    bad.op_1d_host = Q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert call(bad) == -1                                  # Q without w
+    split = sf.SfOpts(); L.sf_opts_init(ctypes.byref(split)); split.precision = 1
+    assert call(split, flux=0) == -2                        # FP32-split is Euler-only
+    assert call(split, fn="dense_hadamard_volume_ex") == -2  # dense is FP64-only
+    # null opts means defaults; E = 0 is still a no-op
+    assert L.sf_hadamard_volume_ex(None, 0, 4, 3, 1, None, None) == 0
+
+
+def test_package_never_imports_oracle():
+    """The product path (package sources, C/HIP sources) has no route to the oracle."""
+    pkg = os.path.join(ROOT, "paper_2306_11665_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".cpp", ".h")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle\b", txt, flags=re.M), fn
+                assert "liboracle" not in txt and "oracle.c" not in txt, fn

@@ -1,0 +1,283 @@
+"""GPU parity: the HIP kernels (through the C-ABI) against the CPU oracle.
+
+Tolerances.  FP64 paths: normwise relative error per conserved variable,
+max_v ||y_gpu - y_ref||_inf / ||y_ref||_inf <= 1e-12.  FP32-split:
+<= 1e-5 with the same metric.  Free-stream elements must also give
+|y| <= 1e-13 max|f(u)|.  Inputs are the seeded synthetic workloads.
+"""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def sf(torch_dev):
+    from paper_2306_11665_amd import sfhad
+    sfhad.lib()
+    return sfhad
+
+
+def normwise(y, ref):
+    """Per-variable (max, mean) normwise relative errors."""
+    nv = ref.shape[0]
+    mx, mn = [], []
+    for v in range(nv):
+        d = np.abs(y[v] - ref[v])
+        s_inf = max(np.abs(ref[v]).max(), 1e-300)
+        s_1 = max(np.abs(ref[v]).sum(), 1e-300)
+        mx.append(d.max() / s_inf)
+        mn.append(d.sum() / s_1)
+    return np.array(mx), np.array(mn)
+
+
+def run_gpu(torch, sf, u, n, d, flux, dense=False, **kw):
+    ut = torch.from_numpy(u).cuda()
+    fn = sf.dense_volume if dense else sf.volume
+    y = fn(ut, n, d, flux, **kw)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def state(flux, E, n, d, seed, fs=0.0):
+    from paper_2306_11665_amd import workloads as W
+    if flux == "euler":
+        return W.euler_state(E, n, seed, fs, d=d)
+    if flux == "product":
+        return W.scalar_state(E, n, d, seed, 1e-8, 30.0)
+    return W.scalar_state(E, n, d, seed)
+
+
+# ----------------------------------------------------------------- workloads
+def test_burgers2d_n4_gll_e64(torch_dev, sf, orc):
+    from paper_2306_11665_amd import workloads as W
+    w = W.WORKLOADS["burgers2d_n4_gll_e64"]
+    u = w.state()
+    y = run_gpu(torch_dev, sf, u, w.n, w.d, w.flux, nodes=w.nodes)
+    ref = orc.dense_volume(u, w.n, w.d, w.flux, nodes_kind=w.nodes)
+    mx, _ = normwise(y, ref)
+    print("burgers2d_n4_gll_e64 max normwise", mx)
+    assert mx.max() <= TOL64
+
+
+def test_euler3d_n4_gl_e4096(torch_dev, sf, orc):
+    from paper_2306_11665_amd import workloads as W
+    w = W.WORKLOADS["euler3d_n4_gl_e4096"]
+    u = w.state()
+    y = run_gpu(torch_dev, sf, u, w.n, w.d, w.flux, nodes=w.nodes)
+    ref = orc.dense_volume(u, w.n, w.d, w.flux, nodes_kind=w.nodes)
+    mx, mn = normwise(y, ref)
+    print("euler3d_n4_gl_e4096 max", mx, "mean", mn)
+    assert mx.max() <= TOL64
+
+
+@pytest.fixture(scope="module")
+def cfg_n8(torch_dev, sf):
+    """The n = 8, 32768-element workload on the GPU (FP64 and FP32-split)."""
+    from paper_2306_11665_amd import workloads as W
+    w = W.WORKLOADS["euler3d_n8_gl_e32768"]
+    u = w.state()
+    ut = torch_dev.from_numpy(u).cuda()
+    y64 = sf.volume(ut, w.n, w.d, w.flux).cpu().numpy()
+    y32 = sf.volume(ut, w.n, w.d, w.flux, precision="fp32_split").cpu().numpy()
+    fs = W.freestream_index(w)
+    sample = W.sample_elements(w.E, 48, seed=33, must_include=fs[:8].tolist() + [0, w.E - 1])
+    return w, u, y64, y32, fs, sample
+
+
+def test_euler3d_n8_gl_e32768_sampled(cfg_n8, orc):
+    w, u, y64, y32, fs, sample = cfg_n8
+    us = np.ascontiguousarray(u[:, sample, :])
+    ref = orc.dense_volume(us, w.n, w.d, w.flux, nodes_kind=w.nodes)
+    mx, mn = normwise(y64[:, sample, :], ref)
+    print(f"euler3d_n8 FP64 on {len(sample)} sampled elements: max {mx} mean {mn}")
+    assert mx.max() <= TOL64
+
+
+def test_euler3d_n8_freestream_elements_vanish(cfg_n8, orc):
+    w, u, y64, y32, fs, sample = cfg_n8
+    assert len(fs) == round(0.1 * w.E)
+    fmax = np.abs(u[:, fs, 0]).max() * 2.0    # |f(u)| <= ~ (E + p)|v| + rho v^2 + p; generous scale
+    fscale = max(np.abs(orc.physical_flux_euler(u[:, e, 0], m)).max() for e in fs[:64] for m in range(3))
+    assert np.abs(y64[:, fs, :]).max() <= 1e-13 * fscale
+    assert np.abs(y32[:, fs, :]).max() <= 1e-5 * fscale
+    del fmax
+
+
+def test_euler3d_n8_full_mesh_vs_oracle_method(cfg_n8, orc):
+    """Every element, against the oracle's CPU sum-factorized method (itself
+    pinned to the dense definition on the CPU)."""
+    w, u, y64, y32, fs, sample = cfg_n8
+    ref = orc.sf_volume(u, w.n, w.d, w.flux, nodes_kind=w.nodes)
+    mx, mn = normwise(y64, ref)
+    print("euler3d_n8 FP64 full mesh max", mx, "mean", mn)
+    assert mx.max() <= TOL64
+    mx32, mn32 = normwise(y32, ref)
+    print("euler3d_n8 FP32-split full mesh max", mx32, "mean", mn32)
+    assert mx32.max() <= TOL32
+
+
+def test_fp32split_sampled_vs_dense_oracle(cfg_n8, orc):
+    w, u, y64, y32, fs, sample = cfg_n8
+    us = np.ascontiguousarray(u[:, sample, :])
+    ref = orc.dense_volume(us, w.n, w.d, w.flux, nodes_kind=w.nodes)
+    mx, mn = normwise(y32[:, sample, :], ref)
+    print("FP32-split sampled: max", mx, "mean", mn)
+    assert mx.max() <= TOL32
+
+
+# ------------------------------------------------------------------ sweeps
+@pytest.mark.parametrize("nodes", ["gl", "gll"])
+@pytest.mark.parametrize("n", list(range(2, 14)))
+def test_euler_all_n(torch_dev, sf, orc, n, nodes):
+    E = 7 if n <= 6 else 3                       # ragged: not a multiple of the block size
+    u = state("euler", E, n, 3, seed=100 + n)
+    y = run_gpu(torch_dev, sf, u, n, 3, "euler", nodes=nodes)
+    ref = orc.dense_volume(u, n, 3, "euler", nodes_kind=nodes)
+    mx, _ = normwise(y, ref)
+    assert mx.max() <= TOL64, (n, nodes, mx)
+
+
+@pytest.mark.parametrize("flux", ["burgers", "product"])
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 7, 8, 9, 11, 12, 16])
+def test_scalar_all_n(torch_dev, sf, orc, flux, d, n):
+    if d == 3 and n >= 12:
+        E = 2
+    else:
+        E = 37 if d == 2 else 5
+    u = state(flux, E, n, d, seed=200 + n)
+    nodes = "gll" if n % 2 else "gl"
+    y = run_gpu(torch_dev, sf, u, n, d, flux, nodes=nodes)
+    ref = orc.dense_volume(u, n, d, flux, nodes_kind=nodes)
+    mx, _ = normwise(y, ref)
+    assert mx.max() <= TOL64, (flux, d, n, mx)
+
+
+@pytest.mark.parametrize("flux,d,n", [("euler", 3, 2), ("euler", 3, 4), ("euler", 3, 5), ("euler", 3, 8),
+                                      ("burgers", 2, 4), ("burgers", 3, 6), ("product", 3, 8),
+                                      ("product", 2, 16)])
+def test_dense_gpu_path(torch_dev, sf, orc, flux, d, n):
+    E = 3
+    u = state(flux, E, n, d, seed=300 + n)
+    y = run_gpu(torch_dev, sf, u, n, d, flux, dense=True)
+    ref = orc.dense_volume(u, n, d, flux)
+    mx, _ = normwise(y, ref)
+    assert mx.max() <= TOL64, mx
+
+
+@pytest.mark.parametrize("n", [2, 4, 5, 8])
+def test_fp32split_small(torch_dev, sf, orc, n):
+    u = state("euler", 9, n, 3, seed=400 + n)
+    y = run_gpu(torch_dev, sf, u, n, 3, "euler", precision="fp32_split")
+    ref = orc.dense_volume(u, n, 3, "euler")
+    mx, _ = normwise(y, ref)
+    assert mx.max() <= TOL32, mx
+
+
+# ------------------------------------------------------------- edge cases
+def test_near_equal_states(torch_dev, sf, orc):
+    """Pairs whose densities / beta differ by 1e-12..1e-2 relative: the series
+    branch and its threshold both sides of 1e-4."""
+    from paper_2306_11665_amd import workloads as W
+    n, E = 6, 12
+    base = W.euler_state(E, n, seed=500, freestream_frac=1.0)
+    rng = np.random.default_rng(501)
+    rho, vel, p = None, None, None
+    u = base.copy()
+    for e in range(E):
+        rel = 10.0 ** (-12 + e)                       # 1e-12 ... 1e-1
+        r = base[0, e] * (1 + rel * rng.uniform(-1, 1, n ** 3))
+        pr = (0.4 * (base[4, e] - 0.5 * (base[1, e] ** 2 + base[2, e] ** 2 + base[3, e] ** 2) / base[0, e]))
+        pr = pr * (1 + rel * rng.uniform(-1, 1, n ** 3))
+        v = base[1:4, e] / base[0, e]
+        u[:, e, :] = W.primitives_to_conserved(r, v, pr)
+    for nodes in ("gl", "gll"):
+        y = run_gpu(torch_dev, sf, u, n, 3, "euler", nodes=nodes)
+        ref = orc.dense_volume(u, n, 3, "euler", nodes_kind=nodes)
+        for e in range(E):
+            mx, _ = normwise(y[:, e:e + 1], ref[:, e:e + 1])
+            # near-equal states give a small y: compare against the flux scale
+            scale = max(np.abs(orc.physical_flux_euler(u[:, e, 0], m)).max() for m in range(3))
+            err = np.abs(y[:, e] - ref[:, e]).max()
+            assert err <= max(TOL64 * np.abs(ref[:, e]).max(), 1e-14 * scale), (nodes, e, err)
+        y32 = run_gpu(torch_dev, sf, u, n, 3, "euler", nodes=nodes, precision="fp32_split")
+        for e in range(E):
+            scale = max(np.abs(orc.physical_flux_euler(u[:, e, 0], m)).max() for m in range(3))
+            err = np.abs(y32[:, e] - ref[:, e]).max()
+            assert err <= max(TOL32 * np.abs(ref[:, e]).max(), 1e-6 * scale), (nodes, e, err)
+
+
+def test_empty_and_single_element(torch_dev, sf, orc):
+    torch = torch_dev
+    u0 = torch.zeros((5, 0, 512), dtype=torch.float64, device="cuda")
+    y0 = sf.volume(u0, 8, 3, "euler")
+    assert y0.shape == (5, 0, 512)
+    u = state("euler", 1, 8, 3, seed=600)
+    y = run_gpu(torch, sf, u, 8, 3, "euler")
+    ref = orc.dense_volume(u, 8, 3, "euler")
+    assert normwise(y, ref)[0].max() <= TOL64
+
+
+def test_bitwise_deterministic(torch_dev, sf):
+    torch = torch_dev
+    u = torch.from_numpy(state("euler", 2000, 8, 3, seed=700, fs=0.1)).cuda()
+    for prec in ("fp64", "fp32_split"):
+        a = sf.volume(u, 8, 3, "euler", precision=prec)
+        b = sf.volume(u, 8, 3, "euler", precision=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), prec
+
+
+def test_operator_override_unweighted_product(torch_dev, sf, orc):
+    """op_1d_host = D, w_1d_host = 1: the paper's sum_j dl/dxi_j o C with C = c c^T."""
+    n, d = 6, 3
+    x, w, D, Q = orc.operator_1d(n, "gl")
+    u = state("product", 4, n, d, seed=800)
+    y = run_gpu(torch_dev, sf, u, n, d, "product", Q=D, w=np.ones(n))
+    ref = orc.dense_volume(u, n, d, "product", Q=D, w=np.ones(n))
+    assert normwise(y, ref)[0].max() <= TOL64
+
+
+def test_gamma_override(torch_dev, sf, orc):
+    u = state("euler", 5, 4, 3, seed=900)
+    y = run_gpu(torch_dev, sf, u, 4, 3, "euler", gamma=5.0 / 3.0)
+    ref = orc.dense_volume(u, 4, 3, "euler", gamma=5.0 / 3.0)
+    assert normwise(y, ref)[0].max() <= TOL64
+
+
+def test_side_stream_and_raw_entry(torch_dev, sf):
+    torch = torch_dev
+    u = torch.from_numpy(state("euler", 300, 5, 3, seed=1000)).cuda()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a = sf.volume(u, 5, 3, "euler", stream=s)
+    s.synchronize()
+    b = torch.empty_like(u)
+    torch.cuda.synchronize()
+    assert sf.volume_raw(u.data_ptr(), 300, 5, 3, 1, b.data_ptr()) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    c = torch.empty_like(u)
+    assert sf.dense_volume_raw(u.data_ptr(), 300, 5, 3, 1, c.data_ptr()) == 0
+    torch.cuda.synchronize()
+    assert (a - c).abs().max().item() <= TOL64 * a.abs().max().item()
+
+
+def test_library_is_the_path(torch_dev, sf):
+    """The product path runs the in-tree HIP library, nothing else."""
+    import ctypes
+    maps = open("/proc/self/maps").read()
+    assert os.path.realpath(sf.LIB_PATH) in maps
