@@ -82,9 +82,11 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=256, help="elements in the CPU-oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=4096, help="elements in the CPU-oracle sample")
     ap.add_argument("--no-extras", action="store_true", help="headline FP64 number only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="also run a plain device-to-device copy of the input's size (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -158,6 +160,17 @@ def main() -> int:
         "device": {"name": props.name, "arch": getattr(props, "gcnArchName", None),
                    "cus": props.multi_processor_count},
     }
+
+    if args.copy_ref:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the HBM-traffic counters of the volume kernel
+        dst = torch.empty_like(ut)
+        for _ in range(3):
+            dst.copy_(ut)
+        torch.cuda.synchronize()
+        result_copy_bytes = ut.numel() * 8
+        log(f"[bench] copy reference: 3 copies of {result_copy_bytes} bytes")
+        del dst
 
     if not args.no_extras:
         # FP32-split form on the same workload
