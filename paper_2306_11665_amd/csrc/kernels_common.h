@@ -128,40 +128,48 @@ struct ScalarFlux {
 
 // ---------------------------------------------------------------------------
 // Chandrashekar's entropy-conserving, kinetic-energy-preserving Euler flux,
-// FP64.  Stored per node: rho, v_x, v_y, v_z, beta = rho / (2 p), ln rho,
-// ln beta.  A lane works in the frame of its line: (v_n, v_t1, v_t2) with
-// n = m, t1 = (m+1) mod 3, t2 = (m+2) mod 3, so the flux code has no
-// direction branches; accumulators are (rho, n-momentum, t1, t2, energy).
+// FP64.  Stored per node: rho, half velocities w = v/2 (so that a sum of two
+// stored values is a mean velocity), beta = rho / (2 p), ln rho, ln beta.  A
+// lane works in the frame of its line: (n, t1, t2) = (m, m+1, m+2) mod 3, so
+// the flux code has no direction branches; accumulators are (rho,
+// n-momentum, t1-momentum, t2-momentum, energy).
 //
-// Logarithmic means: a^ln = (a - b) / (ln a - ln b) from the per-node logs
-// when u = ((a-b)/(a+b))^2 >= 1e-4; below that the series
-// (a + b) / (2 (1 + u/3 + u^2/5 + u^3/7)) (truncation < 1.2e-17 relative),
-// chosen per pair without a branch.  The three quotients of the flux
-// (rho^ln, 1/beta^ln, p_hat = {{rho}}/(2 {{beta}})) share one reciprocal.
+// Logarithmic means a^ln = (a - b)/(ln a - ln b) are carried as a fraction
+// N/D.  With s = a + b, d = a - b and u = d^2/s^2:
+//   u >= 1e-4:  N = d,          D = ln a - ln b          (per-node logs)
+//   u <  1e-4:  N = s^3/2,      D = s^2 + d^2 (1/3 + u/5 + u^2/7)
+// the second being s^2 times the series 1 + u/3 + u^2/5 + u^3/7 of
+// atanh(f)/f, f = d/s (truncation < 1.2e-17 relative; u only enters the
+// terms of size u^2, so a single hardware reciprocal estimate suffices for
+// it).  The form is chosen per pair by selects, not branches.  The three
+// quotients the flux needs -- rho^ln = Nr/Dr, 1/beta^ln = Db/Nb and
+// p_hat = {{rho}}/(2{{beta}}) = (s_rho/2)/s_beta -- share one reciprocal
+// 1/(Dr Nb s_beta).  Valid for rho, beta in about [1e-30, 1e30] (the
+// products of up to six such factors stay in range).
 // ---------------------------------------------------------------------------
 struct EulerNode {
-    double r, vn, vt1, vt2, b, lr, lb;
+    double r, wn, wt1, wt2, b, lr, lb;
 };
 
 struct EulerFP64 {
     using Real = double;
     static constexpr int NV = 5;
     static constexpr int NS = 7;
-    enum { S_R = 0, S_V = 1, S_B = 4, S_LR = 5, S_LB = 6 };
+    enum { S_R = 0, S_W = 1, S_B = 4, S_LR = 5, S_LB = 6 };
     using Node = EulerNode;
     static constexpr double kTau = 1e-4;
 
     // a1: conserved -> stored quantities (FP64, per node).
     __device__ static void stage(const double *uc, double gamma, double *s) {
         double r = uc[0];
-        double ir = 1.0 / r;
+        double ir = rcp_fine(r);
         double v0 = uc[1] * ir, v1 = uc[2] * ir, v2 = uc[3] * ir;
         double p = (gamma - 1.0) * (uc[4] - 0.5 * r * (v0 * v0 + v1 * v1 + v2 * v2));
-        double b = 0.5 * r / p;
+        double b = 0.5 * r * rcp_fine(p);
         s[S_R] = r;
-        s[S_V + 0] = v0;
-        s[S_V + 1] = v1;
-        s[S_V + 2] = v2;
+        s[S_W + 0] = 0.5 * v0;
+        s[S_W + 1] = 0.5 * v1;
+        s[S_W + 2] = 0.5 * v2;
         s[S_B] = b;
         s[S_LR] = log(r);
         s[S_LB] = log(b);
@@ -174,9 +182,9 @@ struct EulerFP64 {
         int t2 = m == 0 ? 2 : m - 1;
         Node A;
         A.r = lds[S_R * arrstride + idx];
-        A.vn = lds[(S_V + m) * arrstride + idx];
-        A.vt1 = lds[(S_V + t1) * arrstride + idx];
-        A.vt2 = lds[(S_V + t2) * arrstride + idx];
+        A.wn = lds[(S_W + m) * arrstride + idx];
+        A.wt1 = lds[(S_W + t1) * arrstride + idx];
+        A.wt2 = lds[(S_W + t2) * arrstride + idx];
         A.b = lds[S_B * arrstride + idx];
         A.lr = lds[S_LR * arrstride + idx];
         A.lb = lds[S_LB * arrstride + idx];
@@ -185,51 +193,52 @@ struct EulerFP64 {
 
     // a4: two-point flux f_n(A, C) in the line frame.  cg = 1 / (2 (gamma - 1)).
     __device__ static void pair(const Node &A, const Node &C, double cg, double *F) {
-        double dr = A.r - C.r, sr = A.r + C.r;
-        double db = A.b - C.b, sb = A.b + C.b;
-        bool near_r = dr * dr < kTau * (sr * sr);
-        bool near_b = db * db < kTau * (sb * sb);
-        double fr = dr * rcp_coarse(sr), fb = db * rcp_coarse(sb);
-        double ur = fr * fr, ub = fb * fb;
-        double Sr = __builtin_fma(ur, __builtin_fma(ur, __builtin_fma(ur, 1.0 / 7.0, 1.0 / 5.0), 1.0 / 3.0), 1.0);
-        double Sb = __builtin_fma(ub, __builtin_fma(ub, __builtin_fma(ub, 1.0 / 7.0, 1.0 / 5.0), 1.0 / 3.0), 1.0);
-        // rho^ln = Nr / Dr ;  1 / beta^ln = Db / Nb
-        // selects, not branches: both forms are computed on every lane
+        const double dr = A.r - C.r, sr = A.r + C.r;
+        const double db = A.b - C.b, sb = A.b + C.b;
+        const double dr2 = dr * dr, sr2 = sr * sr, db2 = db * db, sb2 = sb * sb;
+        const double ur = dr2 * __builtin_amdgcn_rcp(sr2);
+        const double ub = db2 * __builtin_amdgcn_rcp(sb2);
+        const bool near_r = ur < kTau, near_b = ub < kTau;
+        const double hsr = 0.5 * sr, hsb = 0.5 * sb;
+        // series forms (computed on every lane; selected below)
+        const double Nrs = pin(hsr * sr2);
+        const double Drs = pin(__builtin_fma(dr2, __builtin_fma(ur, __builtin_fma(ur, 1.0 / 7.0, 0.2), 1.0 / 3.0), sr2));
+        const double Nbs = pin(hsb * sb2);
+        const double Dbs = pin(__builtin_fma(db2, __builtin_fma(ub, __builtin_fma(ub, 1.0 / 7.0, 0.2), 1.0 / 3.0), sb2));
         const double dlr = pin(A.lr - C.lr), dlb = pin(A.lb - C.lb);
-        Sr = pin(Sr);
-        Sb = pin(Sb);
-        double Nr = near_r ? 0.5 * sr : dr;
-        double Dr = near_r ? Sr : dlr;
-        double Nb = near_b ? 0.5 * sb : db;
-        double Db = near_b ? Sb : dlb;
-        double DrNb = Dr * Nb;
-        double R = rcp_fine(DrNb * sb);
-        double rho_ln = Nr * (Nb * sb) * R;
-        double ibeta_ln = Db * (Dr * sb) * R;
-        double phat = 0.5 * sr * DrNb * R;  // {{rho}} / (2 {{beta}})
+        const double Nr = near_r ? Nrs : dr;
+        const double Dr = near_r ? Drs : dlr;
+        const double Nb = near_b ? Nbs : db;
+        const double Db = near_b ? Dbs : dlb;
+        const double DrNb = Dr * Nb;
+        const double R = rcp_fine(DrNb * sb);
+        const double rho_ln = Nr * (Nb * sb) * R;
+        const double ibeta_ln = Db * (Dr * sb) * R;
+        const double phat = hsr * DrNb * R;
 
-        double Vn = A.vn + C.vn, V1 = A.vt1 + C.vt1, V2 = A.vt2 + C.vt2;  // 2 x means
-        double vv = A.vn * C.vn + A.vt1 * C.vt1 + A.vt2 * C.vt2;          // v_L . v_R
-        double Fr = 0.5 * rho_ln * Vn;
-        double hFr = 0.5 * Fr;
-        F[0] = Fr;
-        F[1] = __builtin_fma(hFr, Vn, phat);
-        F[2] = hFr * V1;
-        F[3] = hFr * V2;
-        // F^E = F^rho [1/(2(gamma-1) beta^ln) + v_L.v_R / 2] + p_hat {{v_n}}
-        F[4] = __builtin_fma(Fr, __builtin_fma(cg, ibeta_ln, 0.5 * vv), 0.5 * phat * Vn);
+        const double vn = A.wn + C.wn, v1 = A.wt1 + C.wt1, v2 = A.wt2 + C.wt2;     // {{v}}
+        const double ww = __builtin_fma(A.wn, C.wn, __builtin_fma(A.wt1, C.wt1, A.wt2 * C.wt2));  // v_L.v_R / 4
+        const double F0 = rho_ln * vn;
+        F[0] = F0;
+        F[1] = __builtin_fma(F0, vn, phat);
+        F[2] = F0 * v1;
+        F[3] = F0 * v2;
+        // F^E = F^rho [1/(2(gamma-1) beta^ln) + v_L.v_R/2] + p_hat {{v_n}}
+        F[4] = __builtin_fma(F0, __builtin_fma(2.0, ww, cg * ibeta_ln), phat * vn);
     }
 
     // Physical flux f_n(u) (the pair flux at equal states), from stored data.
     __device__ static void diag(const Node &A, double gamma, double *F) {
-        double p = 0.5 * A.r / A.b;
-        double rvn = A.r * A.vn;
-        double q = A.vn * A.vn + A.vt1 * A.vt1 + A.vt2 * A.vt2;
+        const double p = 0.5 * A.r * rcp_fine(A.b);
+        const double vn = A.wn + A.wn, v1 = A.wt1 + A.wt1, v2 = A.wt2 + A.wt2;
+        const double rvn = A.r * vn;
+        const double q = __builtin_fma(vn, vn, __builtin_fma(v1, v1, v2 * v2));
         F[0] = rvn;
-        F[1] = __builtin_fma(rvn, A.vn, p);
-        F[2] = rvn * A.vt1;
-        F[3] = rvn * A.vt2;
-        F[4] = A.vn * (gamma / (gamma - 1.0) * p + 0.5 * A.r * q);
+        F[1] = __builtin_fma(rvn, vn, p);
+        F[2] = rvn * v1;
+        F[3] = rvn * v2;
+        // (E + p) v_n with E + p = gamma/(gamma-1) p + rho |v|^2 / 2
+        F[4] = vn * __builtin_fma(gamma / (gamma - 1.0), p, 0.5 * A.r * q);
     }
 
     // Conserved-variable array of accumulator k in direction m's frame.

@@ -27,13 +27,14 @@
 namespace sfhad {
 namespace dev {
 
-// LDS doubles per element array slot: the staged inputs (NS values of type
-// Real) and, after the compute phase, the FP64 outputs (NV values) share it.
-template <class P>
-constexpr int lds_words() {
-    constexpr int in_bytes = P::NS * (int)sizeof(typename P::Real);
-    constexpr int out_bytes = P::NV * 8;
-    return ((in_bytes > out_bytes ? in_bytes : out_bytes) + 7) / 8;
+// Distance between two stored arrays, in elements of size `bytes`: at least
+// `base`, padded so that consecutive arrays start 8 banks apart (the
+// unpadded n = 8 layout puts every array on the same bank).
+template <int bytes>
+constexpr int array_stride(int base) {
+    int as = base;
+    while (((as * bytes / 4) % 32) != 8) ++as;
+    return as;
 }
 
 template <int N, int DIM, class P>
@@ -42,8 +43,11 @@ sf_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int64_t
                  const OpArg<N> op, double gamma) {
     using G = Geom<N, DIM>;
     using R = typename P::Real;
-    constexpr int AS = G::EPB * G::PADN;  // distance between two stored arrays (elements)
-    __shared__ double lds[lds_words<P>() * AS];
+    constexpr int AS = array_stride<(int)sizeof(R)>(G::EPB * G::PADN);  // array distance (elements)
+    // the staged inputs (NS arrays of R) and, after the compute phase, the
+    // FP64 outputs (NV arrays of doubles, same stride) share the buffer
+    constexpr int IN_D = (P::NS * AS * (int)sizeof(R) + 7) / 8, OUT_D = P::NV * AS;
+    __shared__ double lds[IN_D > OUT_D ? IN_D : OUT_D];
     R *lin = reinterpret_cast<R *>(lds);  // staged inputs: NS arrays of type R
     double *lout = lds;                   // outputs: NV arrays of doubles
 
