@@ -141,6 +141,12 @@ const char *sf_last_error(void);
 /* Library version string (static storage). */
 const char *sf_version(void);
 
+/* Diagnostic: y[i] = ln(1 + x[i]) as the kernels' staging step computes it
+ * (the per-node logarithms of rho and beta relative to the element's first
+ * node).  x, y: device arrays of n doubles, x[i] > -1 finite; asynchronous on
+ * `stream` (a hipStream_t, NULL for the null stream).  For tests. */
+int sf_diag_log1p(const double *x, int64_t n, double *y, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of residual-evaluation requests over          */
 /* device-resident meshes of mixed n (one GPU).                               */

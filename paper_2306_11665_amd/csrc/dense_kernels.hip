@@ -38,17 +38,28 @@ dense_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int6
 
     for (int i = tid; i < N * N; i += G::THREADS) sQ[i] = op.Q[i];
     for (int i = tid; i < N; i += G::THREADS) sw[i] = op.w[i];
+    constexpr int NREF = P::NREF > 0 ? P::NREF : 1;
+    __shared__ double sref[NREF];
+    if (P::NREF > 0) {
+        if (tid == 0) {
+            double uc[P::NV];
+#pragma unroll
+            for (int v = 0; v < P::NV; ++v) uc[v] = u[v * vstride + gbase];
+            P::make_ref(uc, gamma, sref);
+        }
+        __syncthreads();
+    }
     for (int i = tid; i < NODES; i += G::THREADS) {
         double uc[P::NV], s[P::NS];
 #pragma unroll
         for (int v = 0; v < P::NV; ++v) uc[v] = u[v * vstride + gbase + i];
-        P::stage(uc, gamma, s);
+        P::stage(uc, sref, gamma, s);
 #pragma unroll
         for (int k = 0; k < P::NS; ++k) lds[k * NODES + i] = s[k];
     }
     __syncthreads();
 
-    const double cg = 0.5 / (gamma - 1.0);
+    const typename P::Consts K = P::consts(0.5 / (gamma - 1.0));
     for (int i = tid; i < NODES; i += G::THREADS) {
         int di[3] = {i % N, (i / N) % N, DIM == 3 ? i / (N * N) : 0};
         double y[P::NV];
@@ -68,7 +79,7 @@ dense_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int6
                     if (k != m) a *= (di[k] == dj[k]) ? sw[di[k]] : 0.0;
                 const typename P::Node J = P::load(lds, NODES, j, m);
                 double F[P::NV];
-                P::pair(I, J, cg, F);
+                P::pair(I, J, K, F);
 #pragma unroll
                 for (int k = 0; k < P::NV; ++k) acc[k] = __builtin_fma(a, F[k], acc[k]);
             }

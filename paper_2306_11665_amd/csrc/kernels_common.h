@@ -87,6 +87,49 @@ __device__ __forceinline__ double rcp_coarse(double x) {
     return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
 }
 
+// ln(1 + x) for finite x > -1, to about one ulp, without a library call.
+// 1 + x = u + e exactly (two-sum); u = 2^k m with m in [sqrt(1/2), sqrt(2));
+// ln(1 + x) = k ln 2 + ln m + e/u.  With f = m - 1 (exact) and s = f/(2 + f),
+// ln m = 2 atanh(s) = f - f^2/2 + s (f^2/2 + R(s^2)), R(z) = sum_j 2 z^j/(2j+1)
+// (|s| <= 0.1716, so nine terms leave a truncation below 1e-17 of ln m); the
+// f - f^2/2 grouping keeps the rounding of s and R out of the leading terms.
+// ln 2 is split so that k * kLn2Hi is exact for |k| < 2^11.
+constexpr double kLn2Hi = 0.6931471805598903;      // 42 leading bits of ln 2
+constexpr double kLn2Lo = 5.497923018708371e-14;   // ln 2 - kLn2Hi
+constexpr double kSqrtHalf = 0.7071067811865476;
+
+__device__ __forceinline__ double log1p_series(double x) {
+    const double u = 1.0 + x;
+    const double bv = u - 1.0;
+    const double e = (1.0 - (u - bv)) + (x - bv);  // 1 + x = u + e exactly
+    int k = __builtin_amdgcn_frexp_exp(u);
+    double m = __builtin_amdgcn_frexp_mant(u);     // u = m 2^k, m in [0.5, 1)
+    if (m < kSqrtHalf) {
+        m = m + m;
+        k -= 1;
+    }
+    const double f = m - 1.0;
+    const double s = f * rcp_fine(2.0 + f);
+    const double z = s * s;
+    double R = 2.0 / 19.0;
+    R = __builtin_fma(R, z, 2.0 / 17.0);
+    R = __builtin_fma(R, z, 2.0 / 15.0);
+    R = __builtin_fma(R, z, 2.0 / 13.0);
+    R = __builtin_fma(R, z, 2.0 / 11.0);
+    R = __builtin_fma(R, z, 2.0 / 9.0);
+    R = __builtin_fma(R, z, 2.0 / 7.0);
+    R = __builtin_fma(R, z, 2.0 / 5.0);
+    R = __builtin_fma(R, z, 2.0 / 3.0);
+    R = R * z;
+    const double hf = 0.5 * f * f;
+    const double lnm = f - (hf - s * (hf + R));
+    const double kd = (double)k;
+    // e / u: for |x| near eps, e is comparable to the result, so the
+    // reciprocal is refined to full precision
+    const double corr = __builtin_amdgcn_ldexp(e, -k) * rcp_fine(m);
+    return __builtin_fma(kd, kLn2Hi, lnm + __builtin_fma(kd, kLn2Lo, corr));
+}
+
 // ---------------------------------------------------------------------------
 // Scalar fluxes (1 variable, one stored quantity per node).
 // ---------------------------------------------------------------------------
@@ -101,14 +144,22 @@ struct ScalarFlux {
     static constexpr int NS = 1;
     using Node = ScalarNode;
 
-    __device__ static void stage(const double *uc, double, double *s) { s[0] = uc[0]; }
+    static constexpr int NREF = 0;
+    __device__ static void make_ref(const double *, double, double *) {}
+    __device__ static void stage(const double *uc, const double *, double, double *s) { s[0] = uc[0]; }
 
     __device__ static Node load(const double *lds, int arrstride, int idx, int) {
         (void)arrstride;
         return Node{lds[idx]};
     }
+    __device__ static Node load_partner(const double *lds, int arrstride, int idx, int m) {
+        return load(lds, arrstride, idx, m);
+    }
 
-    __device__ static void pair(const Node &A, const Node &C, double, double *F) {
+    struct Consts {};
+    __device__ static Consts consts(double) { return Consts{}; }
+
+    __device__ static void pair(const Node &A, const Node &C, const Consts &, double *F) {
         if (KIND == 0)
             F[0] = (A.u * A.u + A.u * C.u + C.u * C.u) * (1.0 / 6.0);
         else
@@ -128,24 +179,30 @@ struct ScalarFlux {
 
 // ---------------------------------------------------------------------------
 // Chandrashekar's entropy-conserving, kinetic-energy-preserving Euler flux,
-// FP64.  Stored per node: rho, half velocities w = v/2 (so that a sum of two
-// stored values is a mean velocity), beta = rho / (2 p), ln rho, ln beta.  A
-// lane works in the frame of its line: (n, t1, t2) = (m, m+1, m+2) mod 3, so
-// the flux code has no direction branches; accumulators are (rho,
-// n-momentum, t1-momentum, t2-momentum, energy).
+// FP64.  Stored per node: rho, half velocities w = v/2 (a sum of two stored
+// values is a mean velocity), beta = rho/(2p), and the logarithms of rho and
+// beta relative to the element's first node,
+//     lr = ln(rho / rho_0) = log1p((rho - rho_0)/rho_0),
+//     lb = cg ln(beta / beta_0),     cg = 1/(2(gamma-1)),
+// so that their rounding error is about eps |ln(a / a_0)|, i.e. scales with
+// the element's own variation rather than with |ln a|.  A lane works in the
+// frame of its line, (n, t1, t2) = (m, m+1, m+2) mod 3, so the flux code has
+// no direction branches; accumulators are (rho, n-, t1-, t2-momentum, E).
 //
 // Logarithmic means a^ln = (a - b)/(ln a - ln b) are carried as a fraction
-// N/D.  With s = a + b, d = a - b and u = d^2/s^2:
-//   u >= 1e-4:  N = d,          D = ln a - ln b          (per-node logs)
-//   u <  1e-4:  N = s^3/2,      D = s^2 + d^2 (1/3 + u/5 + u^2/7)
-// the second being s^2 times the series 1 + u/3 + u^2/5 + u^3/7 of
-// atanh(f)/f, f = d/s (truncation < 1.2e-17 relative; u only enters the
-// terms of size u^2, so a single hardware reciprocal estimate suffices for
-// it).  The form is chosen per pair by selects, not branches.  The three
-// quotients the flux needs -- rho^ln = Nr/Dr, 1/beta^ln = Db/Nb and
-// p_hat = {{rho}}/(2{{beta}}) = (s_rho/2)/s_beta -- share one reciprocal
-// 1/(Dr Nb s_beta).  Valid for rho, beta in about [1e-30, 1e30] (the
-// products of up to six such factors stay in range).
+// N/D.  With s = a + b, d = a - b:
+//   u = d^2/s^2 >= 1e-6:  N = d,      D = lr_a - lr_b  (a difference of
+//                         stored relative logarithms)
+//   u < 1e-6:             N = s^3/2,  D = s^2 + d^2 (1/3 + u/5),
+//                         i.e. s^2 times the series of atanh(f)/f, f = d/s
+//                         (truncation u^3/7 < 1.5e-19; exact equality gives a).
+// The direct form's error, about eps (|ln(a/a_0)| + |ln(b/a_0)|) / |2f|, is
+// below 2 eps/|2f| of the element's own flux variation (~1e-13 at the
+// threshold |f| = 1e-3), for smooth and rough data alike.  The near-equal
+// case is a real branch that waves with no near-equal lane skip.
+// The three quotients the flux needs -- rho^ln = Nr/Dr, 1/beta^ln = Db/Nb
+// and p_hat = {{rho}}/(2{{beta}}) -- share one reciprocal 1/(Dr Nb s_beta).
+// Valid for rho, beta in about [1e-30, 1e30].
 // ---------------------------------------------------------------------------
 struct EulerNode {
     double r, wn, wt1, wt2, b, lr, lb;
@@ -155,24 +212,38 @@ struct EulerFP64 {
     using Real = double;
     static constexpr int NV = 5;
     static constexpr int NS = 7;
+    static constexpr int NREF = 4;  // rho_0, 1/rho_0, beta_0, 1/beta_0
     enum { S_R = 0, S_W = 1, S_B = 4, S_LR = 5, S_LB = 6 };
     using Node = EulerNode;
-    static constexpr double kTau = 1e-4;
+    static constexpr double kSqrtTau = 1e-3;  // |d| < 1e-3 s, i.e. u < 1e-6
+
+    // The element's reference values, from its first node's conserved state.
+    __device__ static void make_ref(const double *uc, double gamma, double *ref) {
+        const double r = uc[0];
+        const double ir = rcp_fine(r);
+        const double v0 = uc[1] * ir, v1 = uc[2] * ir, v2 = uc[3] * ir;
+        const double p = (gamma - 1.0) * (uc[4] - 0.5 * r * (v0 * v0 + v1 * v1 + v2 * v2));
+        const double b = 0.5 * r * rcp_fine(p);
+        ref[0] = r;
+        ref[1] = ir;
+        ref[2] = b;
+        ref[3] = rcp_fine(b);
+    }
 
     // a1: conserved -> stored quantities (FP64, per node).
-    __device__ static void stage(const double *uc, double gamma, double *s) {
-        double r = uc[0];
-        double ir = rcp_fine(r);
-        double v0 = uc[1] * ir, v1 = uc[2] * ir, v2 = uc[3] * ir;
-        double p = (gamma - 1.0) * (uc[4] - 0.5 * r * (v0 * v0 + v1 * v1 + v2 * v2));
-        double b = 0.5 * r * rcp_fine(p);
+    __device__ static void stage(const double *uc, const double *ref, double gamma, double *s) {
+        const double r = uc[0];
+        const double ir = rcp_fine(r);
+        const double v0 = uc[1] * ir, v1 = uc[2] * ir, v2 = uc[3] * ir;
+        const double p = (gamma - 1.0) * (uc[4] - 0.5 * r * (v0 * v0 + v1 * v1 + v2 * v2));
+        const double b = 0.5 * r * rcp_fine(p);
         s[S_R] = r;
         s[S_W + 0] = 0.5 * v0;
         s[S_W + 1] = 0.5 * v1;
         s[S_W + 2] = 0.5 * v2;
         s[S_B] = b;
-        s[S_LR] = log(r);
-        s[S_LB] = log(b);
+        s[S_LR] = log1p_series((r - ref[0]) * ref[1]);
+        s[S_LB] = (0.5 / (gamma - 1.0)) * log1p_series((b - ref[2]) * ref[3]);
     }
 
     // Load node at padded index idx of one element's arrays (arrays are
@@ -191,30 +262,43 @@ struct EulerFP64 {
         return A;
     }
 
-    // a4: two-point flux f_n(A, C) in the line frame.  cg = 1 / (2 (gamma - 1)).
-    __device__ static void pair(const Node &A, const Node &C, double cg, double *F) {
+    __device__ static Node load_partner(const double *lds, int arrstride, int idx, int m) {
+        return load(lds, arrstride, idx, m);
+    }
+
+    // Constants of the pair flux, held in registers for the whole kernel (the
+    // 64-bit ones are not inline operands and would otherwise be rebuilt for
+    // every pair).
+    struct Consts {
+        double cg, sqrt_tau, c3, c5;
+    };
+    __device__ static Consts consts(double cg) {
+        return Consts{pin(cg), pin(kSqrtTau), pin(1.0 / 3.0), pin(0.2)};
+    }
+
+    // a4: two-point flux f_n(A, C) in the line frame (cg is folded into lb).
+    __device__ static void pair(const Node &A, const Node &C, const Consts &K, double *F) {
         const double dr = A.r - C.r, sr = A.r + C.r;
         const double db = A.b - C.b, sb = A.b + C.b;
-        const double dr2 = dr * dr, sr2 = sr * sr, db2 = db * db, sb2 = sb * sb;
-        const double ur = dr2 * __builtin_amdgcn_rcp(sr2);
-        const double ub = db2 * __builtin_amdgcn_rcp(sb2);
-        const bool near_r = ur < kTau, near_b = ub < kTau;
-        const double hsr = 0.5 * sr, hsb = 0.5 * sb;
-        // series forms (computed on every lane; selected below)
-        const double Nrs = pin(hsr * sr2);
-        const double Drs = pin(__builtin_fma(dr2, __builtin_fma(ur, __builtin_fma(ur, 1.0 / 7.0, 0.2), 1.0 / 3.0), sr2));
-        const double Nbs = pin(hsb * sb2);
-        const double Dbs = pin(__builtin_fma(db2, __builtin_fma(ub, __builtin_fma(ub, 1.0 / 7.0, 0.2), 1.0 / 3.0), sb2));
-        const double dlr = pin(A.lr - C.lr), dlb = pin(A.lb - C.lb);
-        const double Nr = near_r ? Nrs : dr;
-        const double Dr = near_r ? Drs : dlr;
-        const double Nb = near_b ? Nbs : db;
-        const double Db = near_b ? Dbs : dlb;
+        double Nr = dr, Dr = A.lr - C.lr;
+        double Nb = db, Db = A.lb - C.lb;
+        if (__builtin_fabs(dr) < K.sqrt_tau * sr) {  // near-equal densities: series
+            const double dr2 = dr * dr, sr2 = sr * sr;
+            const double u = dr2 * __builtin_amdgcn_rcp(sr2);
+            Nr = pin(0.5 * sr * sr2);
+            Dr = __builtin_fma(dr2, __builtin_fma(u, K.c5, K.c3), sr2);
+        }
+        if (__builtin_fabs(db) < K.sqrt_tau * sb) {  // near-equal beta: series, times cg
+            const double db2 = db * db, sb2 = sb * sb;
+            const double u = db2 * __builtin_amdgcn_rcp(sb2);
+            Nb = pin(0.5 * sb * sb2);
+            Db = K.cg * __builtin_fma(db2, __builtin_fma(u, K.c5, K.c3), sb2);
+        }
         const double DrNb = Dr * Nb;
         const double R = rcp_fine(DrNb * sb);
         const double rho_ln = Nr * (Nb * sb) * R;
-        const double ibeta_ln = Db * (Dr * sb) * R;
-        const double phat = hsr * DrNb * R;
+        const double cg_ibeta_ln = Db * (Dr * sb) * R;   // cg / beta^ln
+        const double phat = (0.5 * sr) * DrNb * R;      // {{rho}} / (2 {{beta}})
 
         const double vn = A.wn + C.wn, v1 = A.wt1 + C.wt1, v2 = A.wt2 + C.wt2;     // {{v}}
         const double ww = __builtin_fma(A.wn, C.wn, __builtin_fma(A.wt1, C.wt1, A.wt2 * C.wt2));  // v_L.v_R / 4
@@ -224,7 +308,7 @@ struct EulerFP64 {
         F[2] = F0 * v1;
         F[3] = F0 * v2;
         // F^E = F^rho [1/(2(gamma-1) beta^ln) + v_L.v_R/2] + p_hat {{v_n}}
-        F[4] = __builtin_fma(F0, __builtin_fma(2.0, ww, cg * ibeta_ln), phat * vn);
+        F[4] = __builtin_fma(F0, __builtin_fma(2.0, ww, cg_ibeta_ln), phat * vn);
     }
 
     // Physical flux f_n(u) (the pair flux at equal states), from stored data.
@@ -251,113 +335,148 @@ struct EulerFP64 {
 };
 
 // ---------------------------------------------------------------------------
-// FP32-split form of the Euler flux: the stored quantities, the pair and
-// diagonal fluxes and the line sums are FP32; a logarithmic mean whose
-// arguments are near-equal (u = ((a-b)/(a+b))^2 < 1e-4, tested in FP32) is
-// evaluated from the FP32 arguments in FP64 with the series, then rounded;
-// the direction sum is FP64 (in the kernel).  The per-node logarithms are
-// taken in FP64 and rounded, so ln a - ln b carries only the rounding of the
-// two stored values.
+// FP32-split form of the Euler flux: stored quantities, pair and diagonal
+// fluxes and the line sums are FP32; the direction sum is FP64 (in the
+// kernel).  The per-node logarithms, relative to the element's first node as
+// in the FP64 form, are taken in FP64 of the stored (FP32) rho and beta and
+// kept as two FP32 words (hi + lo), so ln a - ln b of two close states keeps
+// ~1e-16 absolute accuracy and the direct form
+// (a - b)/(ln a - ln b) stays accurate to FP32 rounding until a and b are
+// within about 1e-6 relative.  Below that (u = ((a-b)/(a+b))^2 < 1e-12, tested
+// in FP32, exact equality included) the logarithmic mean is evaluated in FP64
+// by the series and rounded.
 // ---------------------------------------------------------------------------
 struct EulerNodeF {
-    float r, vn, vt1, vt2, b, lr, lb;
+    float r, wn, wt1, wt2, b, p, lrh, lrl, lbh, lbl;
 };
 
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// (a - b) / (ln a - ln b) for near-equal a, b: FP64 series
-// (a + b)/2 * (1 - u/3 - 4u^2/45 - 44u^3/945), u = ((a-b)/(a+b))^2 < 1e-4
-// (the reciprocal of 1 + u/3 + u^2/5 + u^3/7; truncation < 1e-17).
-__device__ __forceinline__ float logmean_near64(float a, float b) {
-    double A = a, B = b;
-    double s = A + B, d = A - B;  // exact for FP32 inputs
-    double f = d * rcp_coarse(s);
-    double u = f * f;
-    double P = __builtin_fma(u, __builtin_fma(u, __builtin_fma(u, -44.0 / 945.0, -4.0 / 45.0), -1.0 / 3.0), 1.0);
-    return (float)(0.5 * s * P);
+// (a - b)/(ln a - ln b) for a, b within 1e-6 relative, in FP64:
+// (a + b)/2 (1 - u/3), u = ((a-b)/(a+b))^2 (the next term, 4u^2/45, is below 1e-24).
+__device__ __forceinline__ double logmean_near64(float a, float b) {
+    const double A = a, B = b;
+    const double s = A + B, d = A - B;  // exact for FP32 inputs
+    const double u = (d * d) * rcp_fine(s * s);
+    return 0.5 * s * __builtin_fma(u, -1.0 / 3.0, 1.0);
 }
 
-// 1 / logmean(a, b) for near-equal a, b: FP64 2 (1 + u/3 + u^2/5 + u^3/7) / (a + b).
-__device__ __forceinline__ float inv_logmean_near64(float a, float b) {
-    double A = a, B = b;
-    double s = A + B, d = A - B;
-    double rs = rcp_fine(s);
-    double f = d * rs;
-    double u = f * f;
-    double S = __builtin_fma(u, __builtin_fma(u, __builtin_fma(u, 1.0 / 7.0, 1.0 / 5.0), 1.0 / 3.0), 1.0);
-    return (float)(2.0 * rs * S);
+// 1 / logmean(a, b) for a, b within 1e-6 relative, in FP64: 2 (1 + u/3) / (a + b).
+__device__ __forceinline__ double inv_logmean_near64(float a, float b) {
+    const double A = a, B = b;
+    const double s = A + B, d = A - B;
+    const double rs = rcp_fine(s);
+    const double f = d * rs;
+    return 2.0 * rs * __builtin_fma(f * f, 1.0 / 3.0, 1.0);
 }
 
 struct EulerFP32Split {
     using Real = float;
     static constexpr int NV = 5;
-    static constexpr int NS = 7;
-    enum { S_R = 0, S_V = 1, S_B = 4, S_LR = 5, S_LB = 6 };
+    static constexpr int NS = 10;
+    enum { S_R = 0, S_W = 1, S_B = 4, S_P = 5, S_LRH = 6, S_LRL = 7, S_LBH = 8, S_LBL = 9 };
     using Node = EulerNodeF;
-    static constexpr float kTau = 1e-4f;
+    static constexpr float kSqrtTau = 1e-6f;
 
-    // a1 in FP64, stored rounded to FP32.
-    __device__ static void stage(const double *uc, double gamma, float *s) {
-        double r = uc[0];
-        double ir = 1.0 / r;
-        double v0 = uc[1] * ir, v1 = uc[2] * ir, v2 = uc[3] * ir;
-        double p = (gamma - 1.0) * (uc[4] - 0.5 * r * (v0 * v0 + v1 * v1 + v2 * v2));
-        double b = 0.5 * r / p;
-        float rf = (float)r, bf = (float)b;
+    // a1 in FP64, stored rounded to FP32; logs (hi, lo) of the stored values.
+    static constexpr int NREF = 4;  // rho_0, 1/rho_0, beta_0, 1/beta_0 (of the FP32-rounded values)
+    __device__ static void make_ref(const double *uc, double gamma, double *ref) {
+        double rf[4];
+        EulerFP64::make_ref(uc, gamma, rf);
+        ref[0] = (double)(float)rf[0];
+        ref[1] = rcp_fine(ref[0]);
+        ref[2] = (double)(float)rf[2];
+        ref[3] = rcp_fine(ref[2]);
+    }
+
+    __device__ static void stage(const double *uc, const double *ref, double gamma, float *s) {
+        const double r = uc[0];
+        const double ir = rcp_fine(r);
+        const double v0 = uc[1] * ir, v1 = uc[2] * ir, v2 = uc[3] * ir;
+        const double p = (gamma - 1.0) * (uc[4] - 0.5 * r * (v0 * v0 + v1 * v1 + v2 * v2));
+        const double b = 0.5 * r * rcp_fine(p);
+        const float rf = (float)r, bf = (float)b;
         s[S_R] = rf;
-        s[S_V + 0] = (float)v0;
-        s[S_V + 1] = (float)v1;
-        s[S_V + 2] = (float)v2;
+        s[S_W + 0] = (float)(0.5 * v0);
+        s[S_W + 1] = (float)(0.5 * v1);
+        s[S_W + 2] = (float)(0.5 * v2);
         s[S_B] = bf;
-        s[S_LR] = (float)log((double)rf);  // logs of the stored (rounded) values
-        s[S_LB] = (float)log((double)bf);
+        s[S_P] = (float)p;
+        const double lr = log1p_series(((double)rf - ref[0]) * ref[1]);
+        const double lb = (0.5 / (gamma - 1.0)) * log1p_series(((double)bf - ref[2]) * ref[3]);
+        const float lrh = (float)lr, lbh = (float)lb;
+        s[S_LRH] = lrh;
+        s[S_LRL] = (float)(lr - (double)lrh);
+        s[S_LBH] = lbh;
+        s[S_LBL] = (float)(lb - (double)lbh);
     }
 
     __device__ static Node load(const float *lds, int arrstride, int idx, int m) {
-        int t1 = m == 2 ? 0 : m + 1;
-        int t2 = m == 0 ? 2 : m - 1;
+        const int t1 = m == 2 ? 0 : m + 1;
+        const int t2 = m == 0 ? 2 : m - 1;
         Node A;
         A.r = lds[S_R * arrstride + idx];
-        A.vn = lds[(S_V + m) * arrstride + idx];
-        A.vt1 = lds[(S_V + t1) * arrstride + idx];
-        A.vt2 = lds[(S_V + t2) * arrstride + idx];
+        A.wn = lds[(S_W + m) * arrstride + idx];
+        A.wt1 = lds[(S_W + t1) * arrstride + idx];
+        A.wt2 = lds[(S_W + t2) * arrstride + idx];
         A.b = lds[S_B * arrstride + idx];
-        A.lr = lds[S_LR * arrstride + idx];
-        A.lb = lds[S_LB * arrstride + idx];
+        A.p = lds[S_P * arrstride + idx];
+        A.lrh = lds[S_LRH * arrstride + idx];
+        A.lrl = lds[S_LRL * arrstride + idx];
+        A.lbh = lds[S_LBH * arrstride + idx];
+        A.lbl = lds[S_LBL * arrstride + idx];
         return A;
     }
 
-    __device__ static void pair(const Node &A, const Node &C, float cg, float *F) {
-        float dr = A.r - C.r, sr = A.r + C.r;
-        float db = A.b - C.b, sb = A.b + C.b;
-        bool near_r = dr * dr < kTau * (sr * sr);
-        bool near_b = db * db < kTau * (sb * sb);
-        float rho_ln = dr * rcpf(A.lr - C.lr);
-        float ibeta_ln = (A.lb - C.lb) * rcpf(db);
-        if (near_r) rho_ln = logmean_near64(A.r, C.r);
-        if (near_b) ibeta_ln = inv_logmean_near64(A.b, C.b);
-        float phat = 0.5f * sr * rcpf(sb);
+    __device__ static Node load_partner(const float *lds, int arrstride, int idx, int m) {
+        Node A = load(lds, arrstride, idx, m);
+        return A;
+    }
 
-        float Vn = A.vn + C.vn, V1 = A.vt1 + C.vt1, V2 = A.vt2 + C.vt2;
-        float vv = A.vn * C.vn + A.vt1 * C.vt1 + A.vt2 * C.vt2;
-        float Fr = 0.5f * rho_ln * Vn;
-        float hFr = 0.5f * Fr;
-        F[0] = Fr;
-        F[1] = __builtin_fmaf(hFr, Vn, phat);
-        F[2] = hFr * V1;
-        F[3] = hFr * V2;
-        F[4] = __builtin_fmaf(Fr, __builtin_fmaf(cg, ibeta_ln, 0.5f * vv), 0.5f * phat * Vn);
+    struct Consts {
+        float cg;
+    };
+    __device__ static Consts consts(double cg) { return Consts{(float)cg}; }
+
+    __device__ static void pair(const Node &A, const Node &C, const Consts &K, float *F) {
+        const float cg = K.cg;
+        const float dr = A.r - C.r, sr = A.r + C.r;
+        const float db = A.b - C.b, sb = A.b + C.b;
+        float Nr = dr, Dr = pin((A.lrh - C.lrh) + (A.lrl - C.lrl));
+        float Nb = db, Db = pin((A.lbh - C.lbh) + (A.lbl - C.lbl));
+        if (__builtin_fabsf(dr) < kSqrtTau * sr) {  // near-identical densities: FP64 series
+            Nr = (float)logmean_near64(A.r, C.r);
+            Dr = 1.0f;
+        }
+        if (__builtin_fabsf(db) < kSqrtTau * sb) {  // near-identical beta: FP64 series
+            Db = (float)((double)cg * inv_logmean_near64(A.b, C.b));
+            Nb = 1.0f;
+        }
+        const float DrNb = Dr * Nb;
+        const float R = rcpf(DrNb * sb);
+        const float rho_ln = Nr * (Nb * sb) * R;
+        const float cg_ibeta_ln = Db * (Dr * sb) * R;
+        const float phat = (0.5f * sr) * DrNb * R;
+
+        const float vn = A.wn + C.wn, v1 = A.wt1 + C.wt1, v2 = A.wt2 + C.wt2;
+        const float ww = __builtin_fmaf(A.wn, C.wn, __builtin_fmaf(A.wt1, C.wt1, A.wt2 * C.wt2));
+        const float F0 = rho_ln * vn;
+        F[0] = F0;
+        F[1] = __builtin_fmaf(F0, vn, phat);
+        F[2] = F0 * v1;
+        F[3] = F0 * v2;
+        F[4] = __builtin_fmaf(F0, __builtin_fmaf(2.0f, ww, cg_ibeta_ln), phat * vn);
     }
 
     __device__ static void diag(const Node &A, double gamma, float *F) {
-        float p = 0.5f * A.r * rcpf(A.b);
-        float rvn = A.r * A.vn;
-        float q = A.vn * A.vn + A.vt1 * A.vt1 + A.vt2 * A.vt2;
+        const float vn = A.wn + A.wn, v1 = A.wt1 + A.wt1, v2 = A.wt2 + A.wt2;
+        const float rvn = A.r * vn;
+        const float q = __builtin_fmaf(vn, vn, __builtin_fmaf(v1, v1, v2 * v2));
         F[0] = rvn;
-        F[1] = __builtin_fmaf(rvn, A.vn, p);
-        F[2] = rvn * A.vt1;
-        F[3] = rvn * A.vt2;
-        F[4] = A.vn * ((float)(gamma / (gamma - 1.0)) * p + 0.5f * A.r * q);
+        F[1] = __builtin_fmaf(rvn, vn, A.p);
+        F[2] = rvn * v1;
+        F[3] = rvn * v2;
+        F[4] = vn * __builtin_fmaf((float)(gamma / (gamma - 1.0)), A.p, 0.5f * A.r * q);
     }
 
     __device__ static int out_array(int k, int m) { return EulerFP64::out_array(k, m); }

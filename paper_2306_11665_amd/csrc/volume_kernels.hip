@@ -58,17 +58,41 @@ sf_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int64_t
     const size_t vstride = (size_t)E * G::NODES;
     const size_t gbase = (size_t)e0 * G::NODES;
 
-    // a1: stage the block's nodes.
-    for (int i = tid; i < nvalid; i += G::THREADS) {
-        double uc[P::NV];
-        R s[P::NS];
+    // a1: per-element reference values (from each element's first node), then
+    // stage the block's nodes.
+    constexpr int NREF = P::NREF > 0 ? P::NREF : 1;
+    __shared__ double sref[G::EPB * NREF];
+    if (P::NREF > 0) {
+        if (tid < nel) {
+            double uc[P::NV];
 #pragma unroll
-        for (int v = 0; v < P::NV; ++v) uc[v] = u[v * vstride + gbase + i];
-        P::stage(uc, gamma, s);
-        const int el = i / G::NODES, node = i - el * G::NODES;
-        const int li = el * G::PADN + G::pidx(node);
+            for (int v = 0; v < P::NV; ++v) uc[v] = u[v * vstride + gbase + (size_t)tid * G::NODES];
+            P::make_ref(uc, gamma, sref + tid * NREF);
+        }
+        __syncthreads();
+    }
+    // every load of the staging pass is issued before any conversion
+    constexpr int SPT = (G::EPB * G::NODES + G::THREADS - 1) / G::THREADS;  // nodes per thread
+    double uc[SPT][P::NV];
 #pragma unroll
-        for (int k = 0; k < P::NS; ++k) lin[k * AS + li] = s[k];
+    for (int k = 0; k < SPT; ++k) {
+        const int i = tid + k * G::THREADS;
+        if (i < nvalid) {
+#pragma unroll
+            for (int v = 0; v < P::NV; ++v) uc[k][v] = u[v * vstride + gbase + i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        const int i = tid + k * G::THREADS;
+        if (i < nvalid) {
+            R s[P::NS];
+            P::stage(uc[k], sref + (i / G::NODES) * NREF, gamma, s);
+            const int el = i / G::NODES, node = i - el * G::NODES;
+            const int li = el * G::PADN + G::pidx(node);
+#pragma unroll
+            for (int q = 0; q < P::NS; ++q) lin[q * AS + li] = s[q];
+        }
     }
     __syncthreads();
 
@@ -81,7 +105,7 @@ sf_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int64_t
     int pbase, pstride, q0, q1;
     line_geometry<N, DIM>(m, line, pbase, pstride, q0, q1);
     const double wperp = DIM == 3 ? op.w[q0] * op.w[q1] : op.w[q0];
-    const R cg = (R)(0.5 / (gamma - 1.0));
+    const typename P::Consts K = P::consts(0.5 / (gamma - 1.0));
     const R *le = lin + el * G::PADN;
 
     R t[N][P::NV];
@@ -103,8 +127,8 @@ sf_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int64_t
             for (int c = a + 1; c < N; ++c) {
                 // re-read node c from LDS for every pair: an opaque index stops
                 // the compiler from keeping the whole line live in registers
-                const typename P::Node C = P::load(le, AS, pin(pbase + c * pstride), m);
-                P::pair(A, C, cg, F);
+                const typename P::Node C = P::load_partner(le, AS, pin(pbase + c * pstride), m);
+                P::pair(A, C, K, F);
                 const R qac = (R)op.Q[a * N + c], qca = (R)op.Q[c * N + a];
 #pragma unroll
                 for (int k = 0; k < P::NV; ++k) {
@@ -123,11 +147,18 @@ sf_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int64_t
     }
     __syncthreads();  // every lane is done reading the staged inputs
 
-    // a6: FP64 direction sum in LDS (the output arrays reuse the input space).
+    // a6: FP64 direction sum in the fixed order m = 0, 1, ..., d-1 (bit
+    // reproducible): the first directions accumulate in LDS (the output
+    // arrays reuse the input space), the last adds its own sums to the LDS
+    // total and stores the result (for fixed a, the lanes of the last
+    // direction cover consecutive nodes: coalesced).
     double *lo = lout + el * G::PADN;
+    const size_t obase = gbase + (size_t)el * G::NODES;
 #pragma unroll
     for (int mm = 0; mm < DIM; ++mm) {
         if (m == mm && active) {
+            const int nstride = DIM == 3 ? N * N : N;  // node stride of the last direction
+            const int nbase = DIM == 3 ? q0 + N * q1 : q0;
 #pragma unroll
             for (int a = 0; a < N; ++a) {
                 const int idx = pbase + a * pstride;
@@ -135,18 +166,16 @@ sf_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int64_t
                 for (int k = 0; k < P::NV; ++k) {
                     double *dst = lo + P::out_array(k, m) * AS + idx;
                     const double val = (double)t[a][k] * wperp;
-                    *dst = mm == 0 ? val : *dst + val;
+                    if (mm == 0)
+                        *dst = val;
+                    else if (mm < DIM - 1)
+                        *dst = *dst + val;
+                    else
+                        out[P::out_array(k, m) * vstride + obase + nbase + a * nstride] = *dst + val;
                 }
             }
         }
-        __syncthreads();
-    }
-
-    for (int i = tid; i < nvalid; i += G::THREADS) {
-        const int e = i / G::NODES, node = i - e * G::NODES;
-        const int li = e * G::PADN + G::pidx(node);
-#pragma unroll
-        for (int v = 0; v < P::NV; ++v) out[v * vstride + gbase + i] = lout[v * AS + li];
+        if (mm < DIM - 1) __syncthreads();
     }
 }
 

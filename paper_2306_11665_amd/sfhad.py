@@ -82,6 +82,8 @@ def lib() -> ctypes.CDLL:
         for name in ("sf_release", "sf_mesh_unregister"):
             getattr(L, name).argtypes = [vp, i64]
             getattr(L, name).restype = ci
+        L.sf_diag_log1p.argtypes = [vp, i64, vp, vp]
+        L.sf_diag_log1p.restype = ci
         L.sf_server_destroy.argtypes = [vp]
         L.sf_server_destroy.restype = ci
         _lib = L
@@ -162,6 +164,17 @@ def volume(u, n: int, d: int, flux: str, **kw):
 def dense_volume(u, n: int, d: int, flux: str, **kw):
     """Same term over all n^(2d) pairs (dense_hadamard_volume_ex)."""
     return _call("dense_hadamard_volume_ex", u, n, d, flux, **kw)
+
+
+def diag_log1p(x, stream=None):
+    """ln(1 + x) by the kernels' staging routine (float64 CUDA tensor in and out)."""
+    import torch
+    if not isinstance(x, torch.Tensor) or x.device.type != "cuda" or x.dtype != torch.float64:
+        raise TypeError("x must be a float64 CUDA tensor")
+    x = x.contiguous()
+    y = torch.empty_like(x)
+    check(lib().sf_diag_log1p(x.data_ptr(), x.numel(), y.data_ptr(), _stream_handle(stream)), "sf_diag_log1p")
+    return y
 
 
 def volume_raw(u_ptr: int, E: int, n: int, d: int, flux: int, out_ptr: int) -> int:
