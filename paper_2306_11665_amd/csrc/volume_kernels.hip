@@ -27,6 +27,45 @@
 namespace sfhad {
 namespace dev {
 
+// a2..a5 for one line: every unordered pair (a < c) once plus the diagonal,
+// accumulated into t.  The loads of the stored arrays are rotated into the
+// frame of direction M.
+template <int N, class P, int M>
+__device__ __forceinline__ void line_pairs(const typename P::Real *le, int AS, int pbase, int pstride,
+                                           const OpArg<N> &op, const typename P::Consts &K, double gamma,
+                                           typename P::Real (&t)[N][P::NV]) {
+    using R = typename P::Real;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        const typename P::Node A = P::load(le, AS, pin(pbase + a * pstride), M);
+        R F[P::NV];
+        P::diag(A, gamma, F);
+        const R qaa = (R)op.Q[a * N + a];
+#pragma unroll
+        for (int k = 0; k < P::NV; ++k) t[a][k] = qaa * F[k] + t[a][k];
+#pragma unroll
+        for (int c = a + 1; c < N; ++c) {
+            // re-read node c from LDS for every pair: an opaque index stops
+            // the compiler from keeping the whole line live in registers
+            const typename P::Node C = P::load_partner(le, AS, pin(pbase + c * pstride), M);
+            P::pair(A, C, K, F);
+            const R qac = (R)op.Q[a * N + c], qca = (R)op.Q[c * N + a];
+#pragma unroll
+            for (int k = 0; k < P::NV; ++k) {
+                t[a][k] = qac * F[k] + t[a][k];
+                t[c][k] = qca * F[k] + t[c][k];
+            }
+            // one pair in flight at a time: its sums complete here, before
+            // the next pair's loads (ordered after this fence) are issued
+#pragma unroll
+            for (int k = 0; k < P::NV; ++k) {
+                t[a][k] = pin(t[a][k]);
+                t[c][k] = pin(t[c][k]);
+            }
+        }
+    }
+}
+
 // Distance between two stored arrays, in elements of size `bytes`: at least
 // `base`, padded so that consecutive arrays start 8 banks apart (the
 // unpadded n = 8 layout puts every array on the same bank).
@@ -115,35 +154,14 @@ sf_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int64_t
         for (int k = 0; k < P::NV; ++k) t[a][k] = (R)0;
 
     if (active) {
-#pragma unroll
-        for (int a = 0; a < N; ++a) {
-            const typename P::Node A = P::load(le, AS, pin(pbase + a * pstride), m);
-            R F[P::NV];
-            P::diag(A, gamma, F);
-            const R qaa = (R)op.Q[a * N + a];
-#pragma unroll
-            for (int k = 0; k < P::NV; ++k) t[a][k] = qaa * F[k] + t[a][k];
-#pragma unroll
-            for (int c = a + 1; c < N; ++c) {
-                // re-read node c from LDS for every pair: an opaque index stops
-                // the compiler from keeping the whole line live in registers
-                const typename P::Node C = P::load_partner(le, AS, pin(pbase + c * pstride), m);
-                P::pair(A, C, K, F);
-                const R qac = (R)op.Q[a * N + c], qca = (R)op.Q[c * N + a];
-#pragma unroll
-                for (int k = 0; k < P::NV; ++k) {
-                    t[a][k] = qac * F[k] + t[a][k];
-                    t[c][k] = qca * F[k] + t[c][k];
-                }
-                // one pair in flight at a time: its sums complete here, before
-                // the next pair's loads (ordered after this fence) are issued
-#pragma unroll
-                for (int k = 0; k < P::NV; ++k) {
-                    t[a][k] = pin(t[a][k]);
-                    t[c][k] = pin(t[c][k]);
-                }
-            }
-        }
+        // m is uniform per wave; one instantiation per direction turns the
+        // rotated array offsets into immediates
+        if (m == 0)
+            line_pairs<N, P, 0>(le, AS, pbase, pstride, op, K, gamma, t);
+        else if (DIM == 2 || m == 1)
+            line_pairs<N, P, 1>(le, AS, pbase, pstride, op, K, gamma, t);
+        else
+            line_pairs<N, P, 2>(le, AS, pbase, pstride, op, K, gamma, t);
     }
     __syncthreads();  // every lane is done reading the staged inputs
 
