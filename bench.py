@@ -77,6 +77,80 @@ def normwise(y, ref):
     return out
 
 
+def serving_leg(torch, W, sfhad, n_req: int, fp64_dof_per_s: float) -> dict:
+    """Poisson arrivals over a pool of device-resident meshes of mixed n."""
+    from paper_2306_11665_amd import serving
+    specs = W.serving_meshes(count=16)
+    log(f"[bench] serving: registering {len(specs)} meshes "
+        f"(n {sorted(set(s.n for s in specs))}, E {min(s.E for s in specs)}..{max(s.E for s in specs)})")
+    out = {"meshes": len(specs), "budget_bytes": 4 << 30, "max_inflight": 256}
+    with serving.Server(4 << 30, max_inflight=256) as srv:
+        meshes = [srv.register(W.serving_mesh_state(s), s.n) for s in specs]
+        # capacity: every mesh served alone (after one warm pass)
+        svc = []
+        for rep in range(3):
+            for m in meshes:
+                t = srv.submit(m.mesh_id)
+                _, lat = srv.wait(t)
+                srv.release(t)
+                if rep:
+                    svc.append(lat)
+        cap = 1.0 / float(np.mean(svc))
+        out["alone_ms_mean"] = float(np.mean(svc) * 1e3)
+        out["capacity_req_per_s"] = cap
+        log(f"[bench] serving: mean service time alone {np.mean(svc) * 1e3:.3f} ms -> capacity {cap:.0f} req/s")
+        warm = max(20, n_req // 10)
+        runs = []
+        for prec, frac in [("fp64", 0.5), ("fp64", 0.8), ("fp64", 0.95), ("fp32_split", 0.8), ("mixed", 0.8)]:
+            arr, which = W.poisson_arrivals(frac * cap, n_req + warm, len(meshes), seed=5)
+            if prec == "mixed":
+                # alternate precisions through two interleaved servers' worth of tickets
+                res = _mixed_run(serving, srv, meshes, arr, which, warm)
+            else:
+                res = serving.run_load(srv, meshes, arr, which, precision=prec, skip=warm)
+            s = res.summary()
+            s.update({"precision": prec, "offered_frac": frac, "offered_req_per_s": frac * cap,
+                      "dof_frac_of_single_request_fp64": s["dof_per_s"] / fp64_dof_per_s})
+            runs.append(s)
+            log(f"[bench] serving {prec} at {frac:.2f} C: p50 {s['p50_ms']:.3f} ms p99 {s['p99_ms']:.3f} ms "
+                f"{s['dof_per_s']:.3e} DOF/s")
+        out["runs"] = runs
+        out["p99_ms_fp64_0.8"] = runs[1]["p99_ms"]
+    return out
+
+
+def _mixed_run(serving, srv, meshes, arr, which, warm):
+    """A Poisson run where requests alternate FP64 / FP32-split."""
+    import threading
+    count = len(arr)
+    tickets = [None] * count
+    lat = np.zeros(count)
+    ready = [threading.Event() for _ in range(count)]
+
+    def consumer():
+        for k in range(count):
+            ready[k].wait()
+            _, lat[k] = srv.wait(tickets[k])
+            srv.release(tickets[k])
+
+    th = threading.Thread(target=consumer, daemon=True)
+    th.start()
+    t0 = time.perf_counter()
+    late = 0.0
+    for k in range(count):
+        target = t0 + arr[k]
+        while time.perf_counter() < target:
+            pass
+        late = max(late, time.perf_counter() - target)
+        tickets[k] = srv.submit(meshes[which[k]].mesh_id, "fp64" if k % 2 == 0 else "fp32_split")
+        ready[k].set()
+    th.join()
+    wall = time.perf_counter() - t0 - arr[warm]
+    dof = sum(meshes[which[k]].dof for k in range(warm, count))
+    el = sum(meshes[which[k]].E for k in range(warm, count))
+    return serving.LoadResult(lat[warm:], count - warm, wall, dof, el, late)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +159,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=4096, help="elements in the CPU-oracle sample")
     ap.add_argument("--no-extras", action="store_true", help="headline FP64 number only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop leg")
+    ap.add_argument("--serve-requests", type=int, default=600, help="measured requests per offered load")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain device-to-device copy of the input's size (counter calibration)")
     args = ap.parse_args()
@@ -231,6 +307,9 @@ def main() -> int:
                                          "dof_per_s": w2.dof / (per_launch * 1e-3),
                                          "elem_evals_per_s": w2.E / (per_launch * 1e-3)}
         log(f"[bench] n=4 E=4096 in a graph: {per_launch * 1e3:.2f} us/launch")
+
+    if not args.no_extras and not args.no_serving:
+        result["serving"] = serving_leg(torch, W, sfhad, args.serve_requests, value)
 
     if not args.no_cpu:
         import oracle

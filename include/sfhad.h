@@ -156,16 +156,33 @@ typedef int64_t sf_mesh;
 typedef int64_t sf_ticket;
 
 /* Create a server on the current device.  hbm_budget_bytes bounds the
- * device memory held by in-flight request outputs; max_inflight bounds the
- * number of requests resident on the device at once (1..1024). */
+ * device memory held by request outputs from admission to sf_release (one
+ * device allocation of that size, sub-allocated first fit); max_inflight
+ * bounds the number of requests holding output memory at once (1..1024).
+ * Requests are admitted in submission order (FIFO).  Each scheduler tick
+ * launches every admitted request in one batch; up to two batches run at
+ * once.  Mesh states are allocated separately (not part of the budget). */
 int sf_server_create(size_t hbm_budget_bytes, int max_inflight, sf_server **out);
 
-/* Register a mesh: the state (layout as above, Euler, d = 3) is copied to a
- * device buffer the server owns.  u_host points to host memory. */
+/* The same scheduler with a simulated device: no HIP call is made, no memory
+ * is allocated, and a batch completes us_per_block microseconds per element
+ * block after it starts (batches run one after another).  y_dev from sf_wait
+ * is NULL.  For capacity planning and host tests. */
+int sf_server_create_sim(size_t hbm_budget_bytes, int max_inflight, double us_per_block,
+                         sf_server **out);
+
+/* Current queue length, requests holding output memory, and budget bytes in
+ * use (any pointer may be NULL). */
+int sf_server_stats(sf_server *srv, int64_t *queued, int64_t *inflight, int64_t *budget_used);
+
+/* Register a mesh: the state (layout as above; Euler flux, d = 3,
+ * 2 <= n <= 8) is copied to a device buffer the server owns.  u_host points
+ * to host memory.  Returns SF_ERR_UNSUPPORTED for other fluxes or n. */
 int sf_mesh_register(sf_server *srv, const double *u_host, int64_t elem_count, int n,
                      int flux_kind, int node_kind, sf_mesh *out);
 
-/* Submit one residual evaluation of a registered mesh (non-blocking). */
+/* Submit one residual evaluation of a registered mesh (non-blocking).
+ * SF_ERR_BUDGET if its output (5 E n^3 doubles) exceeds the whole budget. */
 int sf_submit(sf_server *srv, sf_mesh mesh, int precision, sf_ticket *out);
 
 /* Non-blocking completion check: 1 if done, 0 if not, <0 on error. */
@@ -179,7 +196,9 @@ int sf_wait(sf_server *srv, sf_ticket ticket, const double **y_dev, double *late
 /* Return a completed ticket's output buffer to the budget. */
 int sf_release(sf_server *srv, sf_ticket ticket);
 
+/* Free a mesh; SF_ERR_BUSY while requests on it are not released. */
 int sf_mesh_unregister(sf_server *srv, sf_mesh mesh);
+/* Stop the scheduler, wait for running batches, free everything. */
 int sf_server_destroy(sf_server *srv);
 
 #ifdef __cplusplus

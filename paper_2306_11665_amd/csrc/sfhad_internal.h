@@ -47,6 +47,36 @@ struct VolumeRequest {
 int launch_sf_volume(const VolumeRequest &r);
 int launch_dense_volume(const VolumeRequest &r);
 
+// ---------------------------------------------------------------------------
+// Serving kernel interface (volume_kernels.hip).
+// One request of a batch as the persistent kernel sees it.
+struct ServeDesc {
+    const double *u;     // device state, 5 x E x n^3 (Euler, SoA)
+    double *out;         // device output, same layout
+    int64_t E;           // elements of the mesh
+    int64_t blk_begin;   // first global block index of this request
+    int32_t n;           // nodes per direction, 2..kServeMaxN
+    int32_t prec;        // sf_precision
+    int32_t node_kind;   // sf_node_kind
+    int32_t nblk;        // blocks of this request
+    double gamma;
+};
+constexpr int kServeMaxN = 8;
+constexpr int kServeThreads = 192;
+
+// Blocks (workgroups' work units) a request of E elements with n nodes per
+// direction takes: ceil(E / elements-per-block(n)).
+int64_t serve_blocks(int n, int64_t E);
+// Size in doubles of the operator table and its host-side filling.
+int serve_optable_doubles();
+void serve_fill_optable(double *host);
+// The persistent serving kernel of variant v = prec * 7 + (n - 2), with
+// arguments (const ServeDesc *desc, const int *hdr, const double *optable),
+// hdr = {ndesc, total_blocks} of that variant's requests.
+constexpr int kServeVariants = 14;
+inline int serve_variant(int n, int prec) { return prec * (kServeMaxN - 1) + (n - 2); }
+const void *serve_variant_kernel(int variant);
+
 // Number of conserved variables of a flux kind (0 for an unknown kind).
 inline int flux_nvar(int flux) {
     switch (flux) {

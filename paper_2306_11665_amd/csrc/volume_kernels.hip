@@ -30,9 +30,9 @@ namespace dev {
 // a2..a5 for one line: every unordered pair (a < c) once plus the diagonal,
 // accumulated into t.  The loads of the stored arrays are rotated into the
 // frame of direction M.
-template <int N, class P, int M>
+template <int N, class P, int M, class Op>
 __device__ __forceinline__ void line_pairs(const typename P::Real *le, int AS, int pbase, int pstride,
-                                           const OpArg<N> &op, const typename P::Consts &K, double gamma,
+                                           const Op &op, const typename P::Consts &K, double gamma,
                                            typename P::Real (&t)[N][P::NV]) {
     using R = typename P::Real;
 #pragma unroll
@@ -40,7 +40,7 @@ __device__ __forceinline__ void line_pairs(const typename P::Real *le, int AS, i
         const typename P::Node A = P::load(le, AS, pin(pbase + a * pstride), M);
         R F[P::NV];
         P::diag(A, gamma, F);
-        const R qaa = (R)op.Q[a * N + a];
+        const R qaa = (R)op.q(a * N + a);
 #pragma unroll
         for (int k = 0; k < P::NV; ++k) t[a][k] = qaa * F[k] + t[a][k];
 #pragma unroll
@@ -49,7 +49,7 @@ __device__ __forceinline__ void line_pairs(const typename P::Real *le, int AS, i
             // the compiler from keeping the whole line live in registers
             const typename P::Node C = P::load_partner(le, AS, pin(pbase + c * pstride), M);
             P::pair(A, C, K, F);
-            const R qac = (R)op.Q[a * N + c], qca = (R)op.Q[c * N + a];
+            const R qac = (R)op.q(a * N + c), qca = (R)op.q(c * N + a);
 #pragma unroll
             for (int k = 0; k < P::NV; ++k) {
                 t[a][k] = qac * F[k] + t[a][k];
@@ -76,22 +76,57 @@ constexpr int array_stride(int base) {
     return as;
 }
 
+// LDS needed by one block of the sum-factorized kernel: the staged inputs
+// (NS arrays of Real) and, after the compute phase, the FP64 outputs (NV
+// arrays of doubles, same stride) share the buffer.
 template <int N, int DIM, class P>
-__global__ void __launch_bounds__((Geom<N, DIM>::THREADS))
-sf_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int64_t E,
-                 const OpArg<N> op, double gamma) {
+struct SfLayout {
     using G = Geom<N, DIM>;
     using R = typename P::Real;
-    constexpr int AS = array_stride<(int)sizeof(R)>(G::EPB * G::PADN);  // array distance (elements)
-    // the staged inputs (NS arrays of R) and, after the compute phase, the
-    // FP64 outputs (NV arrays of doubles, same stride) share the buffer
-    constexpr int IN_D = (P::NS * AS * (int)sizeof(R) + 7) / 8, OUT_D = P::NV * AS;
-    __shared__ double lds[IN_D > OUT_D ? IN_D : OUT_D];
+    static constexpr int AS = array_stride<(int)sizeof(R)>(G::EPB * G::PADN);  // array distance (elements)
+    static constexpr int IN_D = (P::NS * AS * (int)sizeof(R) + 7) / 8;
+    static constexpr int OUT_D = P::NV * AS;
+    static constexpr int LDS_D = IN_D > OUT_D ? IN_D : OUT_D;  // doubles
+    static constexpr int NREF = P::NREF > 0 ? P::NREF : 1;
+    static constexpr int REF_D = G::EPB * NREF;                // doubles
+};
+
+// The 1D operator, read from the kernel arguments (standalone launches) or
+// from a device table (the serving kernel).  Both give the same values.
+template <int N>
+struct KernargOp {
+    const OpArg<N> &a;
+    __device__ double q(int i) const { return a.Q[i]; }
+    __device__ double w(int i) const { return a.w[i]; }
+};
+
+struct TableOp {
+    const double *__restrict__ Q;
+    const double *__restrict__ W;
+    // the base is made opaque at every read so that the (scalar) loads stay
+    // next to their use instead of being hoisted and held in registers
+    __device__ double q(int i) const {
+        const double *p = Q;
+        asm volatile("" : "+s"(p));
+        return p[i];
+    }
+    __device__ double w(int i) const { return W[i]; }
+};
+
+// One block of EPB elements starting at element e0 of an E-element mesh:
+// steps a1..a6.  lds holds SfLayout::LDS_D doubles, sref SfLayout::REF_D.
+template <int N, int DIM, class P, class Op>
+__device__ __forceinline__ void sf_block(const double *__restrict__ u, double *__restrict__ out, int64_t E,
+                                         int64_t e0, const Op &op, double gamma, double *lds, double *sref) {
+    using G = Geom<N, DIM>;
+    using L = SfLayout<N, DIM, P>;
+    using R = typename P::Real;
+    constexpr int AS = L::AS;
+    constexpr int NREF = L::NREF;
     R *lin = reinterpret_cast<R *>(lds);  // staged inputs: NS arrays of type R
     double *lout = lds;                   // outputs: NV arrays of doubles
 
     const int tid = threadIdx.x;
-    const int64_t e0 = (int64_t)blockIdx.x * G::EPB;
     const int nel = (int)((E - e0) < G::EPB ? (E - e0) : G::EPB);
     const int nvalid = nel * G::NODES;
     const size_t vstride = (size_t)E * G::NODES;
@@ -99,8 +134,6 @@ sf_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int64_t
 
     // a1: per-element reference values (from each element's first node), then
     // stage the block's nodes.
-    constexpr int NREF = P::NREF > 0 ? P::NREF : 1;
-    __shared__ double sref[G::EPB * NREF];
     if (P::NREF > 0) {
         if (tid < nel) {
             double uc[P::NV];
@@ -143,7 +176,7 @@ sf_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int64_t
     const bool active = el < nel;
     int pbase, pstride, q0, q1;
     line_geometry<N, DIM>(m, line, pbase, pstride, q0, q1);
-    const double wperp = DIM == 3 ? op.w[q0] * op.w[q1] : op.w[q0];
+    const double wperp = DIM == 3 ? op.w(q0) * op.w(q1) : op.w(q0);
     const typename P::Consts K = P::consts(0.5 / (gamma - 1.0));
     const R *le = lin + el * G::PADN;
 
@@ -197,6 +230,16 @@ sf_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int64_t
     }
 }
 
+template <int N, int DIM, class P>
+__global__ void __launch_bounds__((Geom<N, DIM>::THREADS))
+sf_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int64_t E,
+                 const OpArg<N> op, double gamma) {
+    using L = SfLayout<N, DIM, P>;
+    __shared__ double lds[L::LDS_D];
+    __shared__ double sref[L::REF_D];
+    sf_block<N, DIM, P>(u, out, E, (int64_t)blockIdx.x * Geom<N, DIM>::EPB, KernargOp<N>{op}, gamma, lds, sref);
+}
+
 template <int N>
 OpArg<N> make_op(const Operator1D &op) {
     OpArg<N> a;
@@ -240,7 +283,95 @@ int dispatch_n(const VolumeRequest &r) {
     return SF_ERR_UNSUPPORTED;
 }
 
+// ---------------------------------------------------------------------------
+// Serving: a batch of requests of mixed n and precision (3D Euler) runs as
+// one persistent kernel per (precision, n) variant.  Within a variant, global
+// block b belongs to the last request whose blk_begin <= b (a uniform binary
+// search) and runs exactly the code of the standalone kernel (sf_block), so
+// a request's result does not depend on the batch it is served in.  Blocks
+// are visited b = blockIdx.x, + gridDim.x, ... .
+// ---------------------------------------------------------------------------
+constexpr int serve_table_size(int n) { return n < 2 ? 0 : serve_table_size(n - 1) + n * n + n; }
+constexpr int kServeKindDoubles = serve_table_size(kServeMaxN) - serve_table_size(1);
+// offset of Q for (node_kind, n) in the table; w follows Q
+__host__ __device__ constexpr int serve_table_off(int kind, int n) {
+    return kind * kServeKindDoubles + serve_table_size(n - 1);
+}
+
+template <int N, class P>
+__global__ void __launch_bounds__(kServeThreads, 3)
+serve_kernel(const ServeDesc *__restrict__ desc, const int *__restrict__ hdr, const double *__restrict__ optab) {
+    static_assert(Geom<N, 3>::THREADS == kServeThreads, "serving assumes 192-thread blocks");
+    using L = SfLayout<N, 3, P>;
+    __shared__ double lds[L::LDS_D];
+    __shared__ double sref[L::REF_D];
+    const int ndesc = hdr[0];
+    const int total = hdr[1];
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        int lo = 0, hi = ndesc - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (desc[mid].blk_begin <= b) lo = mid; else hi = mid - 1;
+        }
+        lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: keep the descriptor scalar
+        const ServeDesc D = desc[lo];
+        const int off = __builtin_amdgcn_readfirstlane(serve_table_off(D.node_kind, N));
+        const TableOp op{optab + off, optab + off + N * N};
+        sf_block<N, 3, P>(D.u, D.out, D.E, (b - D.blk_begin) * Geom<N, 3>::EPB, op, D.gamma, lds, sref);
+        __syncthreads();  // the next block reuses the LDS
+    }
+}
+
 }  // namespace dev
+
+int64_t serve_blocks(int n, int64_t E) {
+    int epb = 1;
+    switch (n) {
+        case 2: epb = dev::Geom<2, 3>::EPB; break;
+        case 3: epb = dev::Geom<3, 3>::EPB; break;
+        case 4: epb = dev::Geom<4, 3>::EPB; break;
+        case 5: epb = dev::Geom<5, 3>::EPB; break;
+        case 6: epb = dev::Geom<6, 3>::EPB; break;
+        case 7: epb = dev::Geom<7, 3>::EPB; break;
+        case 8: epb = dev::Geom<8, 3>::EPB; break;
+        default: return -1;
+    }
+    return (E + epb - 1) / epb;
+}
+
+int serve_optable_doubles() { return 2 * dev::kServeKindDoubles; }
+
+void serve_fill_optable(double *host) {
+    for (int kind = 0; kind < 2; ++kind)
+        for (int n = 2; n <= kServeMaxN; ++n) {
+            Operator1D op;
+            get_operator(n, kind, op);
+            double *q = host + dev::serve_table_off(kind, n);
+            for (int i = 0; i < n * n; ++i) q[i] = op.Q[i];
+            for (int i = 0; i < n; ++i) q[n * n + i] = op.w[i];
+        }
+}
+
+const void *serve_variant_kernel(int variant) {
+    using namespace dev;
+    switch (variant) {
+        case 0: return reinterpret_cast<const void *>(&serve_kernel<2, EulerFP64>);
+        case 1: return reinterpret_cast<const void *>(&serve_kernel<3, EulerFP64>);
+        case 2: return reinterpret_cast<const void *>(&serve_kernel<4, EulerFP64>);
+        case 3: return reinterpret_cast<const void *>(&serve_kernel<5, EulerFP64>);
+        case 4: return reinterpret_cast<const void *>(&serve_kernel<6, EulerFP64>);
+        case 5: return reinterpret_cast<const void *>(&serve_kernel<7, EulerFP64>);
+        case 6: return reinterpret_cast<const void *>(&serve_kernel<8, EulerFP64>);
+        case 7: return reinterpret_cast<const void *>(&serve_kernel<2, EulerFP32Split>);
+        case 8: return reinterpret_cast<const void *>(&serve_kernel<3, EulerFP32Split>);
+        case 9: return reinterpret_cast<const void *>(&serve_kernel<4, EulerFP32Split>);
+        case 10: return reinterpret_cast<const void *>(&serve_kernel<5, EulerFP32Split>);
+        case 11: return reinterpret_cast<const void *>(&serve_kernel<6, EulerFP32Split>);
+        case 12: return reinterpret_cast<const void *>(&serve_kernel<7, EulerFP32Split>);
+        case 13: return reinterpret_cast<const void *>(&serve_kernel<8, EulerFP32Split>);
+        default: return nullptr;
+    }
+}
 
 int launch_sf_volume(const VolumeRequest &r) {
     using namespace dev;

@@ -1,0 +1,92 @@
+"""GPU tests of the serving loop: served results equal the direct call, and
+each request's result is the same alone and inside a Poisson mix of
+concurrent requests of mixed n and precision (continuous batching)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_2306_11665_amd import serving, sfhad, workloads
+    sfhad.lib()
+    return torch, serving, sfhad, workloads
+
+
+def test_served_result_equals_direct_call(env, orc):
+    torch, serving, sfhad, W = env
+    with serving.Server(1 << 30, max_inflight=16) as srv:
+        for n, E, nodes in [(3, 37, "gl"), (5, 101, "gll"), (8, 40, "gl")]:
+            u = W.euler_state(E, n, seed=1200 + n, freestream_frac=0.1)
+            m = srv.register(u, n, nodes)
+            for prec in ("fp64", "fp32_split"):
+                t = srv.submit(m.mesh_id, prec)
+                y = srv.result(t)
+                srv.release(t)
+                ref = sfhad.volume(torch.from_numpy(u).cuda(), n, 3, "euler", nodes=nodes,
+                                   precision=prec).cpu().numpy()
+                assert np.array_equal(y, ref), (n, prec, np.abs(y - ref).max())
+            orc_ref = orc.dense_volume(u[:, :3], n, 3, "euler", nodes_kind=nodes)
+            t = srv.submit(m.mesh_id, "fp64")
+            y = srv.result(t)[:, :3]
+            srv.release(t)
+            err = max(np.abs(y[v] - orc_ref[v]).max() / np.abs(orc_ref[v]).max() for v in range(5))
+            assert err <= 1e-12, err
+
+
+def test_alone_equals_mix(env):
+    torch, serving, sfhad, W = env
+    specs = [W.MeshSpec(k, n, E, 1300 + k) for k, (n, E) in
+             enumerate([(3, 700), (4, 513), (5, 1200), (6, 333), (7, 900), (8, 640), (8, 2000), (4, 4000)])]
+    with serving.Server(2 << 30, max_inflight=64) as srv:
+        meshes = [srv.register(W.serving_mesh_state(s), s.n) for s in specs]
+        alone = {}
+        for i, m in enumerate(meshes):
+            for prec in ("fp64", "fp32_split"):
+                t = srv.submit(m.mesh_id, prec)
+                alone[(i, prec)] = srv.result(t)
+                srv.release(t)
+        rng = np.random.default_rng(1301)
+        count = 96
+        arr, which = W.poisson_arrivals(20000.0, count, len(meshes), seed=1302)
+        precs = rng.choice(["fp64", "fp32_split"], size=count)
+        # run both precisions in one mix: submit per request with its precision
+        tickets = []
+        import time
+        t0 = time.perf_counter()
+        for k in range(count):
+            while time.perf_counter() - t0 < arr[k]:
+                pass
+            tickets.append(srv.submit(meshes[which[k]].mesh_id, str(precs[k])))
+        max_q = 0
+        for k, t in enumerate(tickets):
+            q, inflight, _ = srv.stats()
+            max_q = max(max_q, inflight)
+            y = srv.result(t)
+            ref = alone[(int(which[k]), str(precs[k]))]
+            assert np.array_equal(y, ref), (k, int(which[k]), str(precs[k]))
+            srv.release(t)
+        print("max requests holding memory at once:", max_q)
+        assert max_q > 1          # requests really overlapped
+
+
+def test_small_budget_forces_queueing(env):
+    torch, serving, sfhad, W = env
+    n, E = 6, 500
+    u = W.euler_state(E, n, seed=1400)
+    nbytes = 5 * E * n ** 3 * 8
+    with serving.Server(int(2.5 * nbytes) + 1024, max_inflight=64) as srv:
+        m = srv.register(u, n)
+        ref = sfhad.volume(torch.from_numpy(u).cuda(), n, 3, "euler").cpu().numpy()
+        ts = [srv.submit(m.mesh_id) for _ in range(12)]
+        q, inflight, used = srv.stats()
+        assert inflight <= 2 and used <= 2.5 * nbytes + 1024
+        for t in ts:
+            y = srv.result(t)
+            assert np.array_equal(y, ref)
+            srv.release(t)
+        assert srv.stats() == (0, 0, 0)
+        srv.unregister(m.mesh_id)
