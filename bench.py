@@ -95,60 +95,31 @@ def serving_leg(torch, W, sfhad, n_req: int, fp64_dof_per_s: float) -> dict:
                 srv.release(t)
                 if rep:
                     svc.append(lat)
-        cap = 1.0 / float(np.mean(svc))
+        cap_alone = 1.0 / float(np.mean(svc))
+        rng = np.random.default_rng(55)
+        burst = rng.integers(0, len(meshes), size=max(64, n_req // 2))
+        serving.saturation_rate(srv, meshes, burst)                       # warm
+        cap = serving.saturation_rate(srv, meshes, burst)
         out["alone_ms_mean"] = float(np.mean(svc) * 1e3)
-        out["capacity_req_per_s"] = cap
-        log(f"[bench] serving: mean service time alone {np.mean(svc) * 1e3:.3f} ms -> capacity {cap:.0f} req/s")
+        out["capacity_alone_req_per_s"] = cap_alone
+        out["capacity_saturated_req_per_s"] = cap
+        log(f"[bench] serving: mean service time alone {np.mean(svc) * 1e3:.3f} ms ({cap_alone:.0f} req/s); "
+            f"saturated {cap:.0f} req/s")
         warm = max(20, n_req // 10)
         runs = []
         for prec, frac in [("fp64", 0.5), ("fp64", 0.8), ("fp64", 0.95), ("fp32_split", 0.8), ("mixed", 0.8)]:
             arr, which = W.poisson_arrivals(frac * cap, n_req + warm, len(meshes), seed=5)
-            if prec == "mixed":
-                # alternate precisions through two interleaved servers' worth of tickets
-                res = _mixed_run(serving, srv, meshes, arr, which, warm)
-            else:
-                res = serving.run_load(srv, meshes, arr, which, precision=prec, skip=warm)
+            precs = prec if prec != "mixed" else ["fp64" if k % 2 == 0 else "fp32_split" for k in range(len(arr))]
+            res = serving.run_load(srv, meshes, arr, which, precision=precs, skip=warm)
             s = res.summary()
-            s.update({"precision": prec, "offered_frac": frac, "offered_req_per_s": frac * cap,
+            s.update({"precision": prec, "offered_frac_of_saturated": frac, "offered_req_per_s": frac * cap,
                       "dof_frac_of_single_request_fp64": s["dof_per_s"] / fp64_dof_per_s})
             runs.append(s)
             log(f"[bench] serving {prec} at {frac:.2f} C: p50 {s['p50_ms']:.3f} ms p99 {s['p99_ms']:.3f} ms "
-                f"{s['dof_per_s']:.3e} DOF/s")
+                f"{s['dof_per_s']:.3e} DOF/s (submit lateness max {s['max_submit_lateness_ms']:.2f} ms)")
         out["runs"] = runs
         out["p99_ms_fp64_0.8"] = runs[1]["p99_ms"]
     return out
-
-
-def _mixed_run(serving, srv, meshes, arr, which, warm):
-    """A Poisson run where requests alternate FP64 / FP32-split."""
-    import threading
-    count = len(arr)
-    tickets = [None] * count
-    lat = np.zeros(count)
-    ready = [threading.Event() for _ in range(count)]
-
-    def consumer():
-        for k in range(count):
-            ready[k].wait()
-            _, lat[k] = srv.wait(tickets[k])
-            srv.release(tickets[k])
-
-    th = threading.Thread(target=consumer, daemon=True)
-    th.start()
-    t0 = time.perf_counter()
-    late = 0.0
-    for k in range(count):
-        target = t0 + arr[k]
-        while time.perf_counter() < target:
-            pass
-        late = max(late, time.perf_counter() - target)
-        tickets[k] = srv.submit(meshes[which[k]].mesh_id, "fp64" if k % 2 == 0 else "fp32_split")
-        ready[k].set()
-    th.join()
-    wall = time.perf_counter() - t0 - arr[warm]
-    dof = sum(meshes[which[k]].dof for k in range(warm, count))
-    el = sum(meshes[which[k]].E for k in range(warm, count))
-    return serving.LoadResult(lat[warm:], count - warm, wall, dof, el, late)
 
 
 def main() -> int:

@@ -12,7 +12,8 @@
 //    one launch: the per-(precision, n) persistent kernels of the batch are
 //    the nodes of a pre-built hipGraph (one graph per in-flight slot, two
 //    slots on two streams, so a new batch starts while the previous one
-//    drains); the descriptors are copied from pinned memory and the nodes'
+//    drains); the batch's descriptors are copied from pinned memory, the
+//    nodes of variants the batch does not use are disabled and the others'
 //    grids set before the graph is replayed.  Requests that arrive while a
 //    batch runs go into the next one.
 //  * Completion is observed by querying each slot's event; latency runs from
@@ -156,8 +157,8 @@ public:
         if (hipMalloc(&optab_, tab.size() * sizeof(double)) != hipSuccess) return fail_hip("hipMalloc optable");
         if (hipMemcpy(optab_, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
             return fail_hip("optable upload");
-        const size_t dbytes = sizeof(ServeDesc) * (size_t)kServeVariants * maxr_;
-        const size_t hbytes = sizeof(int) * 2 * kServeVariants;
+        const size_t dbytes = sizeof(ServeDesc) * (size_t)maxr_;
+        const size_t hbytes = sizeof(int) * 3 * kServeVariants;
         for (int s = 0; s < kSlots; ++s) {
             if (hipStreamCreateWithFlags(&st_[s], hipStreamNonBlocking) != hipSuccess) return fail_hip("stream");
             if (hipEventCreateWithFlags(&ev_[s], hipEventDisableTiming) != hipSuccess) return fail_hip("event");
@@ -194,12 +195,21 @@ public:
     }
 
     int launch(int s, const std::vector<ServeDesc> &descs) override {
-        // group by variant; blk_begin is relative to the variant
+        // descriptors grouped by variant, contiguous; header per variant:
+        // {count, total blocks, first descriptor}; blk_begin is per variant
         int count[kServeVariants] = {0};
+        for (const ServeDesc &d : descs) count[serve_variant(d.n, d.prec)]++;
+        int first[kServeVariants];
+        int acc = 0;
+        for (int v = 0; v < kServeVariants; ++v) {
+            first[v] = acc;
+            acc += count[v];
+        }
+        int fill[kServeVariants] = {0};
         int64_t total[kServeVariants] = {0};
         for (const ServeDesc &d : descs) {
             const int v = serve_variant(d.n, d.prec);
-            ServeDesc &slot = hdesc_[s][(size_t)v * maxr_ + count[v]++];
+            ServeDesc &slot = hdesc_[s][first[v] + fill[v]++];
             slot = d;
             slot.blk_begin = total[v];
             total[v] += d.nblk;
@@ -209,16 +219,24 @@ public:
                 set_error("batch too large for one launch");
                 return SF_ERR_UNSUPPORTED;
             }
-            hhdr_[s][2 * v] = count[v];
-            hhdr_[s][2 * v + 1] = (int)total[v];
+            hhdr_[s][3 * v] = count[v];
+            hhdr_[s][3 * v + 1] = (int)total[v];
+            hhdr_[s][3 * v + 2] = first[v];
         }
-        const size_t dbytes = sizeof(ServeDesc) * (size_t)kServeVariants * maxr_;
-        if (hipMemcpyAsync(ddesc_[s], hdesc_[s], dbytes, hipMemcpyHostToDevice, st_[s]) != hipSuccess ||
-            hipMemcpyAsync(dhdr_[s], hhdr_[s], sizeof(int) * 2 * kServeVariants, hipMemcpyHostToDevice,
+        if (hipMemcpyAsync(ddesc_[s], hdesc_[s], sizeof(ServeDesc) * descs.size(), hipMemcpyHostToDevice,
+                           st_[s]) != hipSuccess ||
+            hipMemcpyAsync(dhdr_[s], hhdr_[s], sizeof(int) * 3 * kServeVariants, hipMemcpyHostToDevice,
                            st_[s]) != hipSuccess)
             return fail_hip("descriptor copy");
         for (int v = 0; v < kServeVariants; ++v) {
-            const int grid = total[v] > 0 ? (int)std::min<int64_t>(total[v], kGridCap) : 1;
+            const bool on = total[v] > 0;
+            if (on != enabled_[s][v]) {
+                if (hipGraphNodeSetEnabled(gexec_[s], node_[s][v], on ? 1 : 0) != hipSuccess)
+                    return fail_hip("graph node enable");
+                enabled_[s][v] = on;
+            }
+            if (!on) continue;
+            const int grid = (int)std::min<int64_t>(total[v], kGridCap);
             if (grid != grid_[s][v]) {
                 hipKernelNodeParams p = params_[s][v];
                 p.gridDim = dim3(grid);
@@ -244,8 +262,8 @@ private:
     int build_graph(int s) {
         if (hipGraphCreate(&graph_[s], 0) != hipSuccess) return fail_hip("hipGraphCreate");
         for (int v = 0; v < kServeVariants; ++v) {
-            args_[s][v].desc = ddesc_[s] + (size_t)v * maxr_;
-            args_[s][v].hdr = dhdr_[s] + 2 * v;
+            args_[s][v].desc = ddesc_[s];
+            args_[s][v].hdr = dhdr_[s] + 3 * v;
             args_[s][v].optab = optab_;
             kargs_[s][v][0] = &args_[s][v].desc;
             kargs_[s][v][1] = &args_[s][v].hdr;
@@ -264,6 +282,7 @@ private:
         }
         if (hipGraphInstantiate(&gexec_[s], graph_[s], nullptr, nullptr, 0) != hipSuccess)
             return fail_hip("hipGraphInstantiate");
+        for (int v = 0; v < kServeVariants; ++v) enabled_[s][v] = true;
         return SF_OK;
     }
 
@@ -284,6 +303,7 @@ private:
     Args args_[kSlots][kServeVariants];
     void *kargs_[kSlots][kServeVariants][3];
     int grid_[kSlots][kServeVariants];
+    bool enabled_[kSlots][kServeVariants];
     ServeDesc *ddesc_[kSlots] = {}, *hdesc_[kSlots] = {};
     int *dhdr_[kSlots] = {}, *hhdr_[kSlots] = {};
 };

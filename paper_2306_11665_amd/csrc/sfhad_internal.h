@@ -72,7 +72,7 @@ int serve_optable_doubles();
 void serve_fill_optable(double *host);
 // The persistent serving kernel of variant v = prec * 7 + (n - 2), with
 // arguments (const ServeDesc *desc, const int *hdr, const double *optable),
-// hdr = {ndesc, total_blocks} of that variant's requests.
+// hdr = {ndesc, total_blocks, first descriptor} of that variant's requests.
 constexpr int kServeVariants = 14;
 inline int serve_variant(int n, int prec) { return prec * (kServeMaxN - 1) + (n - 2); }
 const void *serve_variant_kernel(int variant);

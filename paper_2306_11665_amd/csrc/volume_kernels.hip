@@ -307,6 +307,7 @@ serve_kernel(const ServeDesc *__restrict__ desc, const int *__restrict__ hdr, co
     __shared__ double sref[L::REF_D];
     const int ndesc = hdr[0];
     const int total = hdr[1];
+    desc += hdr[2];
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         int lo = 0, hi = ndesc - 1;
         while (lo < hi) {

@@ -165,12 +165,17 @@ class LoadResult:
         }
 
 
-def run_load(srv: Server, meshes: list, arrivals: np.ndarray, which: np.ndarray, precision: str = "fp64",
+def run_load(srv: Server, meshes: list, arrivals: np.ndarray, which: np.ndarray, precision="fp64",
              collect: bool = False, skip: int = 0) -> LoadResult:
     """Submit request k for mesh meshes[which[k]] at time arrivals[k] (seconds
-    from now); a consumer thread waits, records and releases in submission
-    order.  The first `skip` requests are excluded from the statistics."""
+    from now), with precision `precision` (one name, or one per request); a
+    consumer thread waits, records and releases in submission order.  The
+    first `skip` requests are excluded from the statistics.  The submitting
+    thread only sleeps (no spinning), so the consumer is never starved of the
+    interpreter lock."""
+    import sys
     count = len(arrivals)
+    precs = [precision] * count if isinstance(precision, str) else list(precision)
     tickets = [None] * count
     lat = np.zeros(count)
     done_ev = [threading.Event() for _ in range(count)]
@@ -190,22 +195,24 @@ def run_load(srv: Server, meshes: list, arrivals: np.ndarray, which: np.ndarray,
         except Exception as e:  # surfaced after join
             err.append(e)
 
+    old_switch = sys.getswitchinterval()
+    sys.setswitchinterval(5e-5)
     th = threading.Thread(target=consumer, daemon=True)
     th.start()
     t0 = time.perf_counter()
     late = 0.0
-    for k in range(count):
-        target = t0 + arrivals[k]
-        while True:
+    try:
+        for k in range(count):
+            target = t0 + arrivals[k]
             now = time.perf_counter()
-            if now >= target:
-                break
-            if target - now > 2e-4:
-                time.sleep(min(target - now - 1e-4, 1e-3))
-        late = max(late, time.perf_counter() - target)
-        tickets[k] = srv.submit(meshes[which[k]].mesh_id, precision)
-        done_ev[k].set()
-    th.join()
+            if target > now:
+                time.sleep(target - now)
+            late = max(late, time.perf_counter() - target)
+            tickets[k] = srv.submit(meshes[which[k]].mesh_id, precs[k])
+            done_ev[k].set()
+        th.join()
+    finally:
+        sys.setswitchinterval(old_switch)
     wall = time.perf_counter() - t0
     if err:
         raise err[0]
@@ -214,3 +221,14 @@ def run_load(srv: Server, meshes: list, arrivals: np.ndarray, which: np.ndarray,
     elements = sum(meshes[which[k]].E for k in range(skip, count))
     t_first = arrivals[skip] if skip < count else 0.0
     return LoadResult(lat[sel], count - skip, wall - t_first, dof, elements, late, results)
+
+
+def saturation_rate(srv: Server, meshes: list, which: np.ndarray, precision: str = "fp64") -> float:
+    """Requests per second when `which` is submitted as one burst (the
+    device is never idle): the throughput capacity of the serving loop."""
+    t0 = time.perf_counter()
+    tickets = [srv.submit(meshes[k].mesh_id, precision) for k in which]
+    for t in tickets:
+        srv.wait(t)
+        srv.release(t)
+    return len(which) / (time.perf_counter() - t0)

@@ -55,20 +55,24 @@ def test_requests_arriving_mid_flight_join_the_next_batch(serving):
     with serving.Server(1 << 30, max_inflight=64, sim_us_per_block=5000.0) as srv:   # 40 ms per request
         m = srv.register(tiny_state(E, n), n)
         t0 = srv.submit(m.mesh_id)
-        time.sleep(0.01)                   # t0 is running
-        t1 = srv.submit(m.mesh_id)         # admitted at once (budget and a slot are free)
+        time.sleep(0.005)                  # t0 is launched in one slot,
+        ta = srv.submit(m.mesh_id)
+        time.sleep(0.005)                  # ta in the other
+        t1 = srv.submit(m.mesh_id)         # admitted at once (budget is free) ...
         t2 = srv.submit(m.mesh_id)
         time.sleep(0.005)
         q, inflight, _ = srv.stats()
-        assert q == 0 and inflight == 3
+        assert q == 0 and inflight == 4
         _, l0 = srv.wait(t0)
+        _, la = srv.wait(ta)
         _, l1 = srv.wait(t1)
         _, l2 = srv.wait(t2)
-        # t1 and t2 went to the second slot as one batch: they finish together,
-        # one batch (16 blocks) after t0
+        # ... and wait for a slot: when t0's slot frees they go as one batch
+        # (16 blocks), finish together, after ta
         assert abs(l1 - l2) < 0.01
-        assert l0 < l1
-        for t in (t0, t1, t2):
+        assert l0 < la
+        assert l1 > 0.13                   # 70 ms behind t0 and ta, then 80 ms of their own
+        for t in (t0, ta, t1, t2):
             srv.release(t)
 
 
