@@ -17,6 +17,7 @@ roofline of the dominant kernel and the CPU oracle timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -32,13 +33,48 @@ METRIC = "DOF/s and elem-evals/s, 3D Euler p=7, FP64 vs FP32 split; p99 serve la
 
 # MI355X published peaks
 PEAK_FP64_TFLOPS = 78.6      # vector FP64 (an FMA counts 2 flops): 256 CU x 64 lanes x 2 x 2.4 GHz
-PEAK_FP64_LANE_OPS = 3.93e13  # FP64 VALU lane-operations per second (one per lane per cycle)
+PEAK_FP64_LANE_OPS = 3.93e13  # FP64 VALU lane-operations per second (one per lane per cycle, 2.4 GHz)
 PEAK_HBM_GBS = 8000.0
 
 # Modelled FP64 VALU lane-operations of the method (per unique pair flux
 # including its two Hadamard updates, and per diagonal physical flux).
 OPS_PER_PAIR = 65
 OPS_PER_DIAG = 25
+
+
+# Counter summary of the FP64 n = 8 kernel (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes, scaled by a copy kernel of known size).  Its figures are
+# used only while the kernel's sources are byte-identical to the ones
+# profiled (same digest); otherwise the traffic is reported as unmeasured.
+TRAFFIC_PROFILE = os.path.join("profiles", "sf_volume_kernel_euler_n8_e32768.md")
+KERNEL_SOURCES = [os.path.join("paper_2306_11665_amd", "csrc", f)
+                  for f in ("volume_kernels.hip", "kernels_common.h", "sfhad_internal.h")] + \
+                 [os.path.join("paper_2306_11665_amd", "build.py")]
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_counters() -> dict | None:
+    """The `counters:` line of the committed profile summary as a dict, or
+    None when it is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        for line in f:
+            line = line.strip().strip("`")
+            if line.startswith("counters:"):
+                kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+                if kv.get("digest") != kernel_source_digest():
+                    return None
+                return {k: (v if k == "digest" else float(v)) for k, v in kv.items()}
+    return None
 
 
 def log(msg: str) -> None:
@@ -80,7 +116,7 @@ def normwise(y, ref):
 def serving_leg(torch, W, sfhad, n_req: int, fp64_dof_per_s: float) -> dict:
     """Poisson arrivals over a pool of device-resident meshes of mixed n."""
     from paper_2306_11665_amd import serving
-    specs = W.serving_meshes(count=16)
+    specs = W.serving_meshes(count=64)
     log(f"[bench] serving: registering {len(specs)} meshes "
         f"(n {sorted(set(s.n for s in specs))}, E {min(s.E for s in specs)}..{max(s.E for s in specs)})")
     out = {"meshes": len(specs), "budget_bytes": 4 << 30, "max_inflight": 256}
@@ -95,6 +131,8 @@ def serving_leg(torch, W, sfhad, n_req: int, fp64_dof_per_s: float) -> dict:
                 srv.release(t)
                 if rep:
                     svc.append(lat)
+            if not rep:
+                log("[bench] serving: registered; timing each mesh alone")
         cap_alone = 1.0 / float(np.mean(svc))
         rng = np.random.default_rng(55)
         burst = rng.integers(0, len(meshes), size=max(64, n_req // 2))
@@ -105,7 +143,7 @@ def serving_leg(torch, W, sfhad, n_req: int, fp64_dof_per_s: float) -> dict:
         out["capacity_saturated_req_per_s"] = cap
         log(f"[bench] serving: mean service time alone {np.mean(svc) * 1e3:.3f} ms ({cap_alone:.0f} req/s); "
             f"saturated {cap:.0f} req/s")
-        warm = max(20, n_req // 10)
+        warm = max(20, n_req // 10)                                      # 200 at the default 2000
         runs = []
         for prec, frac in [("fp64", 0.5), ("fp64", 0.8), ("fp64", 0.95), ("fp32_split", 0.8), ("mixed", 0.8)]:
             arr, which = W.poisson_arrivals(frac * cap, n_req + warm, len(meshes), seed=5)
@@ -131,7 +169,7 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="headline FP64 number only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop leg")
-    ap.add_argument("--serve-requests", type=int, default=600, help="measured requests per offered load")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per offered load")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain device-to-device copy of the input's size (counter calibration)")
     args = ap.parse_args()
@@ -170,21 +208,40 @@ def main() -> int:
     log(f"[bench] FP64: {ms_per_step:.4f} ms/step, {value:.4e} DOF/s")
 
     ops = model_ops_per_element(n) * E
-    achieved_lane_ops = ops / (kern_ms * 1e-3)
     bytes_per_launch = 2 * 5 * n ** 3 * 8 * E
+    lane_ops_per_s = ops / (kern_ms * 1e-3)
     roofline = {
         "bound": "alu",
-        "achieved": round(2 * achieved_lane_ops / 1e12, 3),
-        "peak": PEAK_FP64_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(achieved_lane_ops / PEAK_FP64_LANE_OPS, 4),
+        "achieved": round(lane_ops_per_s / 1e12, 3),
+        "peak": PEAK_FP64_LANE_OPS / 1e12,
+        "unit": "TOP/s",
+        "unit_note": "FP64 VALU lane-operations per second (an FMA is one operation); peak = 256 CUs x "
+                     "64 FP64 lanes x 2.4 GHz = 39.3 T/s, the issue rate behind the 78.6 TFLOP/s figure",
+        "frac": round(lane_ops_per_s / PEAK_FP64_LANE_OPS, 4),
         "traffic": None,
         "kernel": "sf_volume_kernel<8,3,EulerFP64>",
         "kernel_ms": round(kern_ms, 5),
         "model_lane_ops_per_element": model_ops_per_element(n),
         "hbm_algorithmic_GBps": round(bytes_per_launch / (kern_ms * 1e-3) / 1e9, 1),
         "hbm_frac": round(bytes_per_launch / (kern_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "algorithmic_bytes_per_launch": bytes_per_launch,
+        "kernel_source_digest": kernel_source_digest(),
     }
+    ctr = profiled_counters()
+    if ctr is not None:
+        # bytes per launch: counters in KiB per dispatch times the copy-kernel calibration
+        roofline["traffic"] = int(round(ctr["fetch_kib"] * 1024 * ctr["fetch_scale"]
+                                        + ctr["write_kib"] * 1024 * ctr["write_scale"]))
+        roofline["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
+        if "f64_wave_insts" in ctr:
+            roofline["measured_f64_lane_ops_per_element"] = round(ctr["f64_wave_insts"] * 64 / E, 1)
+            roofline["measured_valu_f64_issue_util"] = ctr.get("valu_f64_util")
+        if "f64_flops" in ctr:
+            roofline["measured_fp64_TFLOPs"] = round(ctr["f64_flops"] / (kern_ms * 1e-3) / 1e12, 3)
+            roofline["measured_fp64_flop_frac_of_78.6"] = round(
+                ctr["f64_flops"] / (kern_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)
+    log(f"[bench] kernel {roofline['kernel']}: {kern_ms:.4f} ms/launch, model frac {roofline['frac']:.3f}, "
+        f"traffic {'unmeasured for these sources' if ctr is None else roofline['traffic']}")
     result = {
         "metric": METRIC,
         "value": value,

@@ -71,13 +71,24 @@ __device__ __forceinline__ T pin(T x) {
     return x;
 }
 
-// 1/x to (about) one ulp: hardware reciprocal estimate plus two Newton steps.
+// A wave-uniform double moved to scalar registers (both halves read from the
+// first active lane), so constants used by every pair need no vector
+// registers and are not rebuilt from literals at each use.
+__device__ __forceinline__ double uniform_f64(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 1/x to (about) one ulp from the hardware estimate r (relative error
+// |e| < 2^-22, e = 1 - x r): 1/x = r / (1 - e) = r (1 + e + e^2 + O(e^3)),
+// so one third-order correction r + r (e + e^2) replaces two Newton steps
+// (three FMAs instead of four; the dropped e^3 is below 2^-66).
 __device__ __forceinline__ double rcp_fine(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = __builtin_fma(-x, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-x, r, 1.0);
-    return __builtin_fma(r, e, r);
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, __builtin_fma(e, e, e), r);
 }
 
 // 1/x to ~1e-14 relative: estimate plus one Newton step (only used where the
@@ -215,7 +226,10 @@ struct EulerFP64 {
     static constexpr int NREF = 4;  // rho_0, 1/rho_0, beta_0, 1/beta_0
     enum { S_R = 0, S_W = 1, S_B = 4, S_LR = 5, S_LB = 6 };
     using Node = EulerNode;
-    static constexpr double kSqrtTau = 1e-3;  // |d| < 1e-3 s, i.e. u < 1e-6
+    // Series branch when |ln a - ln b| < kLogTau, i.e. |a - b|/(a + b) =
+    // tanh(|ln a - ln b| / 2) < ~1e-3 (u = f^2 < 1e-6); tested on the stored
+    // relative logarithms (one compare, no multiply).
+    static constexpr double kLogTau = 2e-3;
 
     // The element's reference values, from its first node's conserved state.
     __device__ static void make_ref(const double *uc, double gamma, double *ref) {
@@ -266,14 +280,15 @@ struct EulerFP64 {
         return load(lds, arrstride, idx, m);
     }
 
-    // Constants of the pair flux, held in registers for the whole kernel (the
-    // 64-bit ones are not inline operands and would otherwise be rebuilt for
-    // every pair).
+    // Constants of the pair flux, in scalar registers for the whole kernel
+    // (64-bit values that are not inline operands would otherwise be rebuilt
+    // for every pair).  thr_b carries the cg folded into the stored ln beta.
     struct Consts {
-        double cg, sqrt_tau, c3, c5;
+        double cg, c3, c5, thr_r, thr_b;
     };
     __device__ static Consts consts(double cg) {
-        return Consts{pin(cg), pin(kSqrtTau), pin(1.0 / 3.0), pin(0.2)};
+        return Consts{uniform_f64(cg), uniform_f64(1.0 / 3.0), uniform_f64(0.2), uniform_f64(kLogTau),
+                      uniform_f64(kLogTau * cg)};
     }
 
     // a4: two-point flux f_n(A, C) in the line frame (cg is folded into lb).
@@ -282,13 +297,13 @@ struct EulerFP64 {
         const double db = A.b - C.b, sb = A.b + C.b;
         double Nr = dr, Dr = A.lr - C.lr;
         double Nb = db, Db = A.lb - C.lb;
-        if (__builtin_fabs(dr) < K.sqrt_tau * sr) {  // near-equal densities: series
+        if (__builtin_fabs(Dr) < K.thr_r) {  // near-equal densities: series
             const double dr2 = dr * dr, sr2 = sr * sr;
             const double u = dr2 * __builtin_amdgcn_rcp(sr2);
             Nr = pin(0.5 * sr * sr2);
             Dr = __builtin_fma(dr2, __builtin_fma(u, K.c5, K.c3), sr2);
         }
-        if (__builtin_fabs(db) < K.sqrt_tau * sb) {  // near-equal beta: series, times cg
+        if (__builtin_fabs(Db) < K.thr_b) {  // near-equal beta: series, times cg
             const double db2 = db * db, sb2 = sb * sb;
             const double u = db2 * __builtin_amdgcn_rcp(sb2);
             Nb = pin(0.5 * sb * sb2);

@@ -318,7 +318,13 @@ serve_kernel(const ServeDesc *__restrict__ desc, const int *__restrict__ hdr, co
         const ServeDesc D = desc[lo];
         const int off = __builtin_amdgcn_readfirstlane(serve_table_off(D.node_kind, N));
         const TableOp op{optab + off, optab + off + N * N};
-        sf_block<N, 3, P>(D.u, D.out, D.E, (b - D.blk_begin) * Geom<N, 3>::EPB, op, D.gamma, lds, sref);
+        // gamma is uniform per descriptor: keep it (and the flux constants
+        // derived from it) in scalar registers
+        const int64_t gbits = __builtin_bit_cast(int64_t, D.gamma);
+        const int glo = __builtin_amdgcn_readfirstlane((int)(gbits & 0xffffffff));
+        const int ghi = __builtin_amdgcn_readfirstlane((int)(gbits >> 32));
+        const double gamma = __builtin_bit_cast(double, ((int64_t)ghi << 32) | (uint32_t)glo);
+        sf_block<N, 3, P>(D.u, D.out, D.E, (b - D.blk_begin) * Geom<N, 3>::EPB, op, gamma, lds, sref);
         __syncthreads();  // the next block reuses the LDS
     }
 }

@@ -191,7 +191,7 @@ def test_fp32split_small(torch_dev, sf, orc, n):
 def test_near_equal_states(torch_dev, sf, orc):
     """Elements whose nodal densities and pressures differ by 1e-12..1e-1
     relative: exact equality, the near-equal series, the direct form and the
-    switch between them (|d| = 1e-3 s in FP64, 1e-6 s in the FP32 form)."""
+    switch between them (|ln a - ln b| = 2e-3 in FP64, |d| = 1e-6 s in the FP32 form)."""
     from paper_2306_11665_amd import workloads as W
     n, E = 6, 12
     base = W.euler_state(E, n, seed=500, freestream_frac=1.0)
