@@ -63,6 +63,8 @@ def lib():
                           dp, dp, ctypes.c_double, dp]
         L.oracle_sparsity_pattern.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip]
         L.oracle_basis_sparse.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ip, ip, dp]
+        L.oracle_basis_1d.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
+        L.oracle_tensor_apply.argtypes = [dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         L.oracle_set_num_threads.restype = None
@@ -175,6 +177,27 @@ def basis_sparse(n: int, d: int, Q: np.ndarray, w: np.ndarray):
     bs = np.zeros((d, n ** d, n))
     lib().oracle_basis_sparse(n, d, _dp(Q), _dp(w), _ip(rows), _ip(cols), _dp(bs))
     return bs
+
+
+def basis_1d(n: int, kind: str = "gl"):
+    """(V, P): orthonormal Legendre values V[q, k] = L_k(x_q) on the nodes,
+    and the projection P = V^{-1} (P V = I)."""
+    V = np.zeros((n, n)); P = np.zeros((n, n))
+    if lib().oracle_basis_1d(n, NODES[kind], _dp(V), _dp(P)) != 0:
+        raise ValueError("bad arguments or singular basis")
+    return V, P
+
+
+def tensor_apply(u, n: int, d: int, M) -> np.ndarray:
+    """out[v, e] = (M kron ... kron M) u[v, e] (d factors), u of shape (nvar, E, n^d)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    if u.ndim != 3 or u.shape[2] != n ** d or M.shape != (n, n):
+        raise ValueError("shape mismatch")
+    out = np.zeros_like(u)
+    if lib().oracle_tensor_apply(_dp(u), u.shape[1], n, d, u.shape[0], _dp(M), _dp(out)) != 0:
+        raise ValueError("oracle rejected arguments")
+    return out
 
 
 def num_threads() -> int:

@@ -24,6 +24,12 @@
  *     oracle_sf_volume below restate those steps for d = 3 (and the d = 2
  *     form that follows from Eq. (2)).
  *
+ *   - Eq. (6) and the proof of Theorem 1: a polynomial basis chi evaluated
+ *     on the nodes, its projection Pi with Pi chi = I, and the basis
+ *     transformation applied direction by direction.  oracle_basis_1d and
+ *     oracle_tensor_apply below give the plain definition of that
+ *     transformation (one dense Kronecker-power matrix per element).
+ *
  * The primary oracle is oracle_dense_volume: it builds every A_m as an
  * explicit Kronecker product (n^d x n^d), evaluates the two-point flux on ALL
  * n^(2d) node pairs and sums the Hadamard product row by row, with no
@@ -433,6 +439,93 @@ int oracle_sf_volume(const double *u, long E, int n, int d, int flux,
 }
 
 /* Thread count OpenMP will use (1 without OpenMP). */
+/* ------------------------------------------------------------------------ */
+/* Basis transformation (Eq. (6), proof of Theorem 1)                        */
+/* ------------------------------------------------------------------------ */
+
+/* chi: orthonormal Legendre polynomials on [-1,1], L_k = sqrt((2k+1)/2) P_k
+ * (the paper leaves the modal basis open; this is the reading taken).
+ * V[q*n + k] = L_k(x_q) on the n nodes of the given kind, and
+ * P = V^{-1} (the projection with P V = I), by Gauss-Jordan elimination with
+ * partial pivoting.  Returns 0, or -1 on bad arguments / a singular V. */
+int oracle_basis_1d(int n, int kind, double *V, double *P)
+{
+    if (n < 1 || n > 64 || !V) return -1;
+    double x[64], w[64];
+    if (oracle_nodes(n, kind, x, w) != 0) return -1;
+    for (int q = 0; q < n; ++q)
+        for (int k = 0; k < n; ++k) {
+            double Pk, dPk;
+            legendre(k, x[q], &Pk, &dPk);
+            V[q * n + k] = sqrt((2.0 * k + 1.0) / 2.0) * Pk;
+        }
+    if (!P) return 0;
+    /* [V | I] -> [I | V^{-1}] */
+    double *aug = (double *)malloc(sizeof(double) * (size_t)n * 2 * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < 2 * n; ++j)
+            aug[i * 2 * n + j] = j < n ? V[i * n + j] : (j - n == i ? 1.0 : 0.0);
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < n; ++i)
+            if (fabs(aug[i * 2 * n + c]) > fabs(aug[piv * 2 * n + c])) piv = i;
+        if (aug[piv * 2 * n + c] == 0.0) { free(aug); return -1; }
+        if (piv != c)
+            for (int j = 0; j < 2 * n; ++j) {
+                double t = aug[c * 2 * n + j];
+                aug[c * 2 * n + j] = aug[piv * 2 * n + j];
+                aug[piv * 2 * n + j] = t;
+            }
+        double d = aug[c * 2 * n + c];
+        for (int j = 0; j < 2 * n; ++j) aug[c * 2 * n + j] /= d;
+        for (int i = 0; i < n; ++i) {
+            if (i == c) continue;
+            double f = aug[i * 2 * n + c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < 2 * n; ++j) aug[i * 2 * n + j] -= f * aug[c * 2 * n + j];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) P[i * n + j] = aug[i * 2 * n + n + j];
+    free(aug);
+    return 0;
+}
+
+/* out_e = (M (x) ... (x) M) in_e for every element and variable: the d-fold
+ * Kronecker power of the 1D matrix M (n x n, row-major), built explicitly
+ * (n^d x n^d, z (x) y (x) x so that node ix + n iy + n^2 iz is the row
+ * index) and applied as a dense matrix-vector product.  With M = V this is
+ * the modal-to-nodal transformation u = chi(xi) u_hat; with M = P the
+ * projection back.  Same layout as the volume term; nvar variables. */
+int oracle_tensor_apply(const double *in, long E, int n, int d, int nvar, const double *M, double *out)
+{
+    if (!in || !out || !M || E < 0 || n < 1 || d < 1 || d > 3 || nvar < 1) return -1;
+    int N = 1;
+    for (int k = 0; k < d; ++k) N *= n;
+    double *K = (double *)malloc(sizeof(double) * (size_t)N * N);
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)N * N);
+    int size = n;
+    memcpy(K, M, sizeof(double) * n * n);
+    for (int k = 1; k < d; ++k) {
+        kron(K, size, size, M, n, n, tmp);
+        size *= n;
+        memcpy(K, tmp, sizeof(double) * (size_t)size * size);
+    }
+    free(tmp);
+#pragma omp parallel for schedule(static)
+    for (long ev = 0; ev < E * nvar; ++ev) {
+        const double *x = in + (size_t)ev * N;
+        double *y = out + (size_t)ev * N;
+        for (int i = 0; i < N; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < N; ++j) s += K[(size_t)i * N + j] * x[j];
+            y[i] = s;
+        }
+    }
+    free(K);
+    return 0;
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP
