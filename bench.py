@@ -310,6 +310,32 @@ def main() -> int:
         log(f"[bench] dense: {msd:.2f} ms for {Es} elements -> sf is "
             f"{(msd / Es) / ms_sf_per_elem:.1f}x faster per element")
 
+        # basis transformation on the FP64 matrix cores: nodal -> modal on the
+        # same state (5 variables x 32768 elements, n = 8), HBM-bound
+        V1, P1 = sfhad.basis_1d(n, "gl")
+        ti = torch.empty_like(ut)
+
+        def stept():
+            sfhad.tensor_apply(ut, n, 3, P1, out=ti, stream=stream)
+
+        for _ in range(args.warmup):
+            stept()
+        tt, kt = timed_launches(torch, stept, args.steps, stream)
+        tbytes = 2 * ut.numel() * 8
+        tflops = 2 * 3 * n * ut.numel()                   # d passes of n MACs per value
+        result["tensor_apply"] = {
+            "what": "sf_tensor_apply, projection P = V^-1 of the orthonormal Legendre basis, "
+                    "5 x 32768 slabs of 8^3 (FP64 MFMA 16x16x4)",
+            "ms_per_launch": kt, "elem_evals_per_s": E / (kt * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": round(tbytes / (kt * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(tbytes / (kt * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                         "traffic": None, "algorithmic_bytes_per_launch": tbytes,
+                         "fp64_TFLOPs_algorithmic": round(tflops / (kt * 1e-3) / 1e12, 3)},
+        }
+        log(f"[bench] tensor_apply n=8: {kt * 1e3:.1f} us/launch, "
+            f"{tbytes / (kt * 1e-3) / 1e9:.0f} GB/s ({tbytes / (kt * 1e-3) / 1e9 / PEAK_HBM_GBS:.2f} of HBM peak)")
+        del ti
+
         # n = 4 workload: 100 launches captured in one HIP graph
         w2 = W.WORKLOADS["euler3d_n4_gl_e4096"]
         u2 = torch.from_numpy(w2.state()).cuda()

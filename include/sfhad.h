@@ -127,6 +127,35 @@ int dense_hadamard_volume_ex(const double *u_nodes, int64_t elem_count, int n, i
  * doubles; any of them may be NULL.  No GPU needed. */
 int sf_operator_1d(int n, int node_kind, double *x_host, double *w_host, double *Q_host);
 
+/* ---------------------------------------------------------------------
+ * Basis transformation (Eq. (6) and the proof of Theorem 1): a modal
+ * polynomial basis chi evaluated on the nodes, and its projection Pi with
+ * Pi chi = I, applied direction by direction (sum factorization), turns
+ * modal coefficients into the nodal values the volume term takes, and back.
+ * --------------------------------------------------------------------- */
+
+/* The 1D modal basis: orthonormal Legendre polynomials on [-1, 1],
+ * V[q*n + k] = sqrt((2k+1)/2) P_k(x_q) on the n nodes of node_kind, and its
+ * projection P = V^{-1} (P V = I).  Host buffers of n*n doubles, row-major;
+ * either may be NULL.  No GPU needed.  SF_ERR_ARG for n < 1 or an unknown
+ * node kind, SF_ERR_UNSUPPORTED for n outside [2, 16]. */
+int sf_basis_1d(int n, int node_kind, double *V_host, double *P_host);
+
+/* out_e = (M (x) ... (x) M) in_e (d factors, the factor of direction m acting
+ * on the index along m) for every element e and variable: with M = V the
+ * modal coefficients u_hat become nodal values, with M = P the reverse.
+ *   in, out   device, nvar * E * n^d doubles, layout [v][e][node] with
+ *             node = ix + n iy + n^2 iz (the modal index is ordered the
+ *             same way: kx + n ky + n^2 kz).  out may equal in (in place);
+ *             any other overlap is SF_ERR_ARG.  out is fully overwritten.
+ *   E >= 0 (0 is a no-op), 2 <= n <= 16, d in {2, 3}, nvar >= 1
+ *   M_host    host, n*n doubles, row-major, finite; copied before return
+ *   stream    a hipStream_t, NULL for the null stream; asynchronous.
+ * FP64 throughout (the passes run on the FP64 matrix cores).  Errors as for
+ * sf_hadamard_volume, all detected before any HIP call except SF_ERR_HIP. */
+int sf_tensor_apply(const double *in, int64_t elem_count, int n, int d, int nvar,
+                    const double *M_host, double *out, void *stream);
+
 /* Select the HIP device for the calling thread and build the operators for
  * every n up to n_max (optional warm-up; the first call per shape otherwise
  * does it).  Returns SF_ERR_HIP when no device is usable. */

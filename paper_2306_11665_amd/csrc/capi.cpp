@@ -4,7 +4,7 @@
 #include <cstring>
 #include <string>
 
-#include "sfhad_internal.h"
+#include "tensor_internal.h"
 
 namespace sfhad {
 
@@ -164,6 +164,47 @@ int sf_init(int device, int n_max) {
         get_operator(n, SF_NODES_GAUSS_LOBATTO, op);
     }
     return SF_OK;
+}
+
+int sf_basis_1d(int n, int node_kind, double *V, double *P) {
+    if (n < 1) return fail(SF_ERR_ARG, "n must be >= 1");
+    if (node_kind != SF_NODES_GAUSS_LEGENDRE && node_kind != SF_NODES_GAUSS_LOBATTO)
+        return fail(SF_ERR_ARG, "unknown node_kind");
+    if (n < SF_MIN_N || n > SF_MAX_N) return fail(SF_ERR_UNSUPPORTED, "n outside [2, 16]");
+    if (!build_basis(n, node_kind, V, P)) return fail(SF_ERR_UNSUPPORTED, "basis construction failed");
+    return SF_OK;
+}
+
+int sf_tensor_apply(const double *in, int64_t E, int n, int d, int nvar, const double *M_host, double *out,
+                    void *stream) {
+    if (E < 0) return fail(SF_ERR_ARG, "elem_count must be >= 0");
+    if (n < 1) return fail(SF_ERR_ARG, "n must be >= 1");
+    if (d < 1) return fail(SF_ERR_ARG, "d must be >= 1");
+    if (nvar < 1) return fail(SF_ERR_ARG, "nvar must be >= 1");
+    if (!M_host) return fail(SF_ERR_ARG, "null M_host");
+    if (d > 3 || d == 1) return fail(SF_ERR_UNSUPPORTED, "d must be 2 or 3");
+    if (n < SF_MIN_N || n > SF_MAX_N) return fail(SF_ERR_UNSUPPORTED, "n outside [2, 16]");
+    const int64_t N = ipow(n, d);
+    if (E > 0 && E > INT64_MAX / (N * nvar * (int64_t)sizeof(double)))
+        return fail(SF_ERR_ARG, "elem_count too large");
+    for (int i = 0; i < n * n; ++i)
+        if (!std::isfinite(M_host[i])) return fail(SF_ERR_ARG, "M_host has a non-finite entry");
+    if (E == 0) return SF_OK;
+    if (!in || !out) return fail(SF_ERR_ARG, "null in or out");
+    const size_t bytes = (size_t)(N * nvar * E) * sizeof(double);
+    const char *ib = reinterpret_cast<const char *>(in), *ob = reinterpret_cast<const char *>(out);
+    if (ib != ob && ib < ob + bytes && ob < ib + bytes)
+        return fail(SF_ERR_ARG, "out partially overlaps in (only in == out is allowed)");
+    TensorRequest r;
+    r.in = in;
+    r.out = out;
+    r.E = E;
+    r.n = n;
+    r.d = d;
+    r.nvar = nvar;
+    r.stream = reinterpret_cast<hipStream_t>(stream);
+    for (int i = 0; i < n * n; ++i) r.M[i] = M_host[i];
+    return launch_tensor_apply(r);
 }
 
 const char *sf_status_string(int status) {

@@ -13,7 +13,7 @@
 // D_ij = prod_{k != i,j} (x_i - x_k) / prod_{k != j} (x_j - x_k); the
 // diagonal is minus the off-diagonal row sum, so that D 1 = 0 to rounding
 // (a constant state then gives a zero volume term).
-#include "sfhad_internal.h"
+#include "tensor_internal.h"
 
 #include <cmath>
 #include <mutex>
@@ -155,6 +155,39 @@ bool get_operator(int n, int node_kind, Operator1D &op) {
         if (!build_operator(n, node_kind, cache[n])) return false;
     }
     op = cache[n];
+    return true;
+}
+
+// Modal basis for the basis transformation: orthonormal Legendre
+// polynomials L_k = sqrt((2k+1)/2) P_k evaluated on the n nodes,
+// V[q][k] = L_k(x_q).  Its projection P = V^{-1} in closed form: the
+// quadrature makes V^T W V = G diagonal -- the identity for Gauss-Legendre
+// (exact to degree 2n - 1), and for Gauss-Lobatto the identity except
+// G[N][N] = (2N + 1)/N (N = n - 1; the rule is exact to degree 2n - 3 and
+// sums P_N^2 to 2/N) -- so P = G^{-1} V^T W.
+bool build_basis(int n, int node_kind, double *V, double *P) {
+    Operator1D op;
+    if (!get_operator(n, node_kind, op)) return false;
+    double Vl[kMaxN * kMaxN];
+    for (int q = 0; q < n; ++q) {
+        const double x = op.x[q];
+        double pkm1 = 0.0, pk = 1.0;  // P_{-1}, P_0
+        for (int k = 0; k < n; ++k) {
+            Vl[q * n + k] = std::sqrt((2.0 * k + 1.0) / 2.0) * pk;
+            const double pkp1 = ((2.0 * k + 1.0) * x * pk - k * pkm1) / (k + 1.0);
+            pkm1 = pk;
+            pk = pkp1;
+        }
+    }
+    if (V)
+        for (int i = 0; i < n * n; ++i) V[i] = Vl[i];
+    if (P) {
+        const int N = n - 1;
+        for (int k = 0; k < n; ++k) {
+            const double g = (node_kind == SF_NODES_GAUSS_LOBATTO && k == N) ? (2.0 * N + 1.0) / N : 1.0;
+            for (int q = 0; q < n; ++q) P[k * n + q] = Vl[q * n + k] * op.w[q] / g;
+        }
+    }
     return true;
 }
 

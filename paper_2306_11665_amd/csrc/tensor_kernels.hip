@@ -1,0 +1,184 @@
+// Sum-factorized basis transformation (the step the proof of Theorem 1 adds
+// in front of the Hadamard product): out_e = (M (x) ... (x) M) in_e for every
+// element and variable, applied as d one-dimensional passes (Eq. (6): the
+// modal basis chi evaluated on the nodes, M = V, or its projection, M = P).
+//
+// Each pass is a small dense contraction: for direction m, every grid line L
+// of a slab (one element's values of one variable, n^d doubles) maps
+// Y_L[q] = sum_k M[q][k] X_L[k].  It runs on the FP64 matrix cores:
+// v_mfma_f64_16x16x4f64 computes D(16 x 16) += A(16 x 4) B(4 x 16) with
+//   A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
+//   D[i][j] in lane j + 16 (i % 4), accumulator register i / 4
+// (the layout verified on gfx950).  Here i = output node q (n <= 16 of the
+// 16 rows used), j = one of 16 lines, k = input node, ceil(n / 4) steps.
+//
+// The work is HBM-bound (2 x 8 bytes per value moved against 2 d n flops),
+// so a block streams G slabs (about 2048 values) through LDS: coalesced
+// loads of all its slabs, d - 1 passes LDS to LDS, and the last pass written
+// from the MFMA accumulators straight to HBM (for the last direction the 16
+// lines of a tile are 16 consecutive nodes: 128-byte segments).  A block
+// only writes the slabs it read, after a barrier, so in == out is allowed.
+#include "tensor_internal.h"
+
+namespace sfhad {
+namespace dev {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTensorThreads = 256;
+
+template <int N>
+struct MatArg {
+    double M[N * N];
+};
+
+template <int N, int DIM>
+struct TensorGeom {
+    static constexpr int NODES = DIM == 3 ? N * N * N : N * N;
+    static constexpr int LINES = NODES / N;                          // lines per slab and direction
+    static constexpr int G = NODES >= 2048 ? 1 : 2048 / NODES;        // slabs per block
+    static constexpr int PADN = NODES + LINES;                       // one pad slot per x-row
+    static constexpr int KS = (N + 3) / 4;                           // MFMA k-steps
+    static constexpr int TILES = (G * LINES + 15) / 16;              // 16-line tiles per pass
+};
+
+// padded LDS index of node `nd` of slab g
+template <int N, int DIM>
+__device__ __forceinline__ int tpad(int g, int nd) {
+    return g * TensorGeom<N, DIM>::PADN + nd + nd / N;
+}
+
+// node of line L, position k, in direction m (x fastest)
+template <int N, int DIM>
+__device__ __forceinline__ int tnode(int L, int k, int m) {
+    if (DIM == 2) return m == 0 ? k + N * L : L + N * k;
+    if (m == 0) return k + N * L;                         // L = y + n z
+    if (m == 1) return (L % N) + N * k + N * N * (L / N);  // L = x + n z
+    return L + N * N * k;                                 // L = x + n y
+}
+
+template <int N, int DIM>
+__global__ void __launch_bounds__(kTensorThreads)
+tensor_apply_kernel(const double *__restrict__ in, double *out, int64_t slabs, MatArg<N> M) {
+    using G = TensorGeom<N, DIM>;
+    __shared__ double buf[2][G::G * G::PADN];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int64_t s0 = (int64_t)blockIdx.x * G::G;
+    const int gs = (int)((slabs - s0) < G::G ? (slabs - s0) : G::G);  // slabs in this block
+    const int nvals = gs * G::NODES;
+    const double *src = in + s0 * G::NODES;
+
+    // coalesced load of the block's slabs (every load issued before any store)
+    constexpr int PER = (G::G * G::NODES + kTensorThreads - 1) / kTensorThreads;
+    double v[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int i = tid + j * kTensorThreads;
+        v[j] = i < nvals ? src[i] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int i = tid + j * kTensorThreads;
+        if (i < nvals) buf[0][tpad<N, DIM>(i / G::NODES, i % G::NODES)] = v[j];
+    }
+
+    // A operand per k-step: M[q][k], q = lane % 16, k = 4 s + lane / 16
+    double a[G::KS];
+    const int q_a = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < G::KS; ++s) {
+        const int k = 4 * s + kq;
+        a[s] = (q_a < N && k < N) ? M.M[q_a * N + k] : 0.0;
+    }
+    __syncthreads();
+
+    const int nlines = gs * G::LINES;
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+        const double *X = buf[m & 1];
+        double *Y = buf[(m + 1) & 1];
+        for (int t = wave; t < G::TILES; t += kTensorThreads / 64) {
+            const int Lg = t * 16 + (lane & 15);  // this lane's line (B column, D column)
+            const bool lok = Lg < nlines;
+            const int g = lok ? Lg / G::LINES : 0;
+            const int L = lok ? Lg % G::LINES : 0;
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < G::KS; ++s) {
+                const int k = 4 * s + kq;
+                const double b = (lok && k < N) ? X[tpad<N, DIM>(g, tnode<N, DIM>(L, k, m))] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b, acc, 0, 0, 0);
+            }
+            // D[q][line] in register r, q = 4 r + lane / 16
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int q = 4 * r + kq;
+                if (!lok || q >= N) continue;
+                const int nd = tnode<N, DIM>(L, q, m);
+                if (m == DIM - 1)
+                    out[(s0 + g) * G::NODES + nd] = acc[r];
+                else
+                    Y[tpad<N, DIM>(g, nd)] = acc[r];
+            }
+        }
+        if (m < DIM - 1) __syncthreads();
+    }
+}
+
+template <int N, int DIM>
+int launch_tensor(const TensorRequest &r) {
+    using G = TensorGeom<N, DIM>;
+    MatArg<N> M;
+    for (int i = 0; i < N * N; ++i) M.M[i] = r.M[i];
+    const int64_t slabs = r.E * r.nvar;
+    const int64_t blocks = (slabs + G::G - 1) / G::G;
+    if (blocks > 0x7fffffffLL) {
+        set_error("too many elements for one launch");
+        return SF_ERR_UNSUPPORTED;
+    }
+    hipLaunchKernelGGL((tensor_apply_kernel<N, DIM>), dim3((unsigned)blocks), dim3(kTensorThreads), 0, r.stream,
+                       r.in, r.out, slabs, M);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) {
+        set_error(std::string("tensor_apply_kernel launch: ") + hipGetErrorString(err));
+        return SF_ERR_HIP;
+    }
+    return SF_OK;
+}
+
+template <int DIM>
+int dispatch_tensor(const TensorRequest &r) {
+    switch (r.n) {
+        case 2: return launch_tensor<2, DIM>(r);
+        case 3: return launch_tensor<3, DIM>(r);
+        case 4: return launch_tensor<4, DIM>(r);
+        case 5: return launch_tensor<5, DIM>(r);
+        case 6: return launch_tensor<6, DIM>(r);
+        case 7: return launch_tensor<7, DIM>(r);
+        case 8: return launch_tensor<8, DIM>(r);
+        case 9: return launch_tensor<9, DIM>(r);
+        case 10: return launch_tensor<10, DIM>(r);
+        case 11: return launch_tensor<11, DIM>(r);
+        case 12: return launch_tensor<12, DIM>(r);
+        case 13: return launch_tensor<13, DIM>(r);
+        case 14: return launch_tensor<14, DIM>(r);
+        case 15: return launch_tensor<15, DIM>(r);
+        case 16: return launch_tensor<16, DIM>(r);
+        default:
+            set_error("n outside [2, 16]");
+            return SF_ERR_UNSUPPORTED;
+    }
+}
+
+}  // namespace dev
+
+int launch_tensor_apply(const TensorRequest &r) {
+    if (r.d == 2) return dev::dispatch_tensor<2>(r);
+    if (r.d == 3) return dev::dispatch_tensor<3>(r);
+    set_error("d must be 2 or 3");
+    return SF_ERR_UNSUPPORTED;
+}
+
+}  // namespace sfhad

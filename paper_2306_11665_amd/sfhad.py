@@ -82,6 +82,10 @@ def lib() -> ctypes.CDLL:
         for name in ("sf_release", "sf_mesh_unregister"):
             getattr(L, name).argtypes = [vp, i64]
             getattr(L, name).restype = ci
+        L.sf_basis_1d.argtypes = [ci, ci, _dp, _dp]
+        L.sf_basis_1d.restype = ci
+        L.sf_tensor_apply.argtypes = [vp, i64, ci, ci, ci, _dp, vp, vp]
+        L.sf_tensor_apply.restype = ci
         L.sf_diag_log1p.argtypes = [vp, i64, vp, vp]
         L.sf_diag_log1p.restype = ci
         L.sf_server_destroy.argtypes = [vp]
@@ -164,6 +168,34 @@ def volume(u, n: int, d: int, flux: str, **kw):
 def dense_volume(u, n: int, d: int, flux: str, **kw):
     """Same term over all n^(2d) pairs (dense_hadamard_volume_ex)."""
     return _call("dense_hadamard_volume_ex", u, n, d, flux, **kw)
+
+
+def basis_1d(n: int, nodes: str = "gl"):
+    """(V, P) of the library's modal basis: orthonormal Legendre values
+    V[q, k] on the nodes and the projection P = V^{-1} (host, FP64)."""
+    V = np.zeros((n, n)); P = np.zeros((n, n))
+    check(lib().sf_basis_1d(n, NODES[nodes], V.ctypes.data_as(_dp), P.ctypes.data_as(_dp)), "sf_basis_1d")
+    return V, P
+
+
+def tensor_apply(u, n: int, d: int, M, *, out=None, stream=None):
+    """out[v, e] = (M kron ... kron M) u[v, e] (sf_tensor_apply); u is a
+    contiguous float64 CUDA tensor (nvar, E, n^d); out may be u itself."""
+    import torch
+    if not isinstance(u, torch.Tensor) or u.device.type != "cuda" or u.dtype != torch.float64:
+        raise TypeError("u must be a float64 CUDA tensor")
+    if not u.is_contiguous() or u.dim() != 3 or u.shape[2] != n ** d:
+        raise ValueError(f"u must be a contiguous (nvar, E, {n ** d}) tensor, got {tuple(u.shape)}")
+    if out is None:
+        out = torch.empty_like(u)
+    elif out.shape != u.shape or out.dtype != u.dtype or not out.is_contiguous() or out.device != u.device:
+        raise ValueError("out must match u")
+    Mh = np.ascontiguousarray(M, dtype=np.float64)
+    if Mh.shape != (n, n):
+        raise ValueError(f"M must be ({n}, {n})")
+    check(lib().sf_tensor_apply(u.data_ptr(), u.shape[1], n, d, u.shape[0], Mh.ctypes.data_as(_dp),
+                                out.data_ptr(), _stream_handle(stream)), "sf_tensor_apply")
+    return out
 
 
 def diag_log1p(x, stream=None):

@@ -132,3 +132,39 @@ def test_package_never_imports_oracle():
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle\b", txt, flags=re.M), fn
                 assert "liboracle" not in txt and "oracle.c" not in txt, fn
+
+
+@pytest.mark.parametrize("kind", ["gl", "gll"])
+@pytest.mark.parametrize("n", [2, 3, 4, 8, 13, 16])
+def test_basis_matches_oracle(sf, orc, n, kind):
+    """The library's modal basis (recurrence) and its closed-form projection
+    against the oracle's basis and Gauss-Jordan inverse."""
+    V, P = sf.basis_1d(n, kind)
+    Vo, Po = orc.basis_1d(n, kind)
+    assert np.abs(V - Vo).max() <= 1e-14 * np.abs(Vo).max()
+    assert np.abs(P - Po).max() <= 1e-12 * np.abs(Po).max()
+    assert np.abs(P @ V - np.eye(n)).max() < 1e-13
+
+
+def test_tensor_apply_validation(sf):
+    L = sf.lib()
+    M = np.eye(4)
+    Mp = M.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    f = L.sf_tensor_apply
+    assert f(None, 4, 4, 3, 5, Mp, None, None) == -1          # null pointers
+    assert f(BAD, -1, 4, 3, 5, Mp, BAD + 10 ** 9, None) == -1  # negative E
+    assert f(BAD, 4, 0, 3, 5, Mp, BAD + 10 ** 9, None) == -1   # n < 1
+    assert f(BAD, 4, 4, 0, 5, Mp, BAD + 10 ** 9, None) == -1   # d < 1
+    assert f(BAD, 4, 4, 3, 0, Mp, BAD + 10 ** 9, None) == -1   # nvar < 1
+    assert f(BAD, 4, 4, 3, 5, None, BAD + 10 ** 9, None) == -1  # null M
+    assert f(BAD, 4, 17, 3, 5, Mp, BAD + 10 ** 9, None) == -2  # n > 16
+    assert f(BAD, 4, 1, 3, 5, Mp, BAD + 10 ** 9, None) == -2   # n = 1
+    assert f(BAD, 4, 4, 4, 5, Mp, BAD + 10 ** 9, None) == -2   # d = 4
+    assert f(BAD, 4, 4, 3, 5, Mp, BAD + 8, None) == -1         # partial overlap
+    Mn = np.eye(4); Mn[1, 2] = np.inf
+    assert f(BAD, 4, 4, 3, 5, Mn.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), BAD + 10 ** 9, None) == -1
+    assert f(None, 0, 4, 3, 5, Mp, None, None) == 0           # E = 0: no-op
+    assert L.sf_basis_1d(0, 0, None, None) == -1
+    assert L.sf_basis_1d(4, 3, None, None) == -1
+    assert L.sf_basis_1d(17, 0, None, None) == -2
+    assert L.sf_basis_1d(4, 1, None, None) == 0
