@@ -13,11 +13,14 @@
 // 16 rows used), j = one of 16 lines, k = input node, ceil(n / 4) steps.
 //
 // The work is HBM-bound (2 x 8 bytes per value moved against 2 d n flops),
-// so a block streams G slabs (about 2048 values) through LDS: coalesced
-// loads of all its slabs, d - 1 passes LDS to LDS, and the last pass written
-// from the MFMA accumulators straight to HBM (for the last direction the 16
-// lines of a tile are 16 consecutive nodes: 128-byte segments).  A block
-// only writes the slabs it read, after a barrier, so in == out is allowed.
+// so a block streams G slabs (at most 2048 values and 256 lines) through one
+// LDS buffer: coalesced loads of all its slabs, d - 1 passes that keep their
+// (at most 4) tiles in registers and overwrite the buffer after a barrier,
+// and the last pass written from the MFMA accumulators straight to HBM (for
+// the last direction the 16 lines of a tile are 16 consecutive nodes:
+// 128-byte segments).  One buffer instead of two doubles the blocks, and so
+// the loads in flight, per CU.  A block only writes the slabs it read, after
+// a barrier, so in == out is allowed.
 #include "tensor_internal.h"
 
 namespace sfhad {
@@ -36,10 +39,13 @@ template <int N, int DIM>
 struct TensorGeom {
     static constexpr int NODES = DIM == 3 ? N * N * N : N * N;
     static constexpr int LINES = NODES / N;                          // lines per slab and direction
-    static constexpr int G = NODES >= 2048 ? 1 : 2048 / NODES;        // slabs per block
+    static constexpr int GV = NODES >= 2048 ? 1 : 2048 / NODES;      // by values per block
+    static constexpr int GL = LINES >= 256 ? 1 : 256 / LINES;        // by lines per block
+    static constexpr int G = GV < GL ? GV : GL;                      // slabs per block
     static constexpr int PADN = NODES + LINES;                       // one pad slot per x-row
     static constexpr int KS = (N + 3) / 4;                           // MFMA k-steps
     static constexpr int TILES = (G * LINES + 15) / 16;              // 16-line tiles per pass
+    static constexpr int TPW = (TILES + 3) / 4;                      // tiles per wave (<= 4)
 };
 
 // padded LDS index of node `nd` of slab g
@@ -61,7 +67,8 @@ template <int N, int DIM>
 __global__ void __launch_bounds__(kTensorThreads)
 tensor_apply_kernel(const double *__restrict__ in, double *out, int64_t slabs, MatArg<N> M) {
     using G = TensorGeom<N, DIM>;
-    __shared__ double buf[2][G::G * G::PADN];
+    static_assert(G::TPW <= 4, "at most 4 tiles per wave are held in registers");
+    __shared__ double buf[G::G * G::PADN];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -81,7 +88,7 @@ tensor_apply_kernel(const double *__restrict__ in, double *out, int64_t slabs, M
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int i = tid + j * kTensorThreads;
-        if (i < nvals) buf[0][tpad<N, DIM>(i / G::NODES, i % G::NODES)] = v[j];
+        if (i < nvals) buf[tpad<N, DIM>(i / G::NODES, i % G::NODES)] = v[j];
     }
 
     // A operand per k-step: M[q][k], q = lane % 16, k = 4 s + lane / 16
@@ -97,33 +104,45 @@ tensor_apply_kernel(const double *__restrict__ in, double *out, int64_t slabs, M
     const int nlines = gs * G::LINES;
 #pragma unroll
     for (int m = 0; m < DIM; ++m) {
-        const double *X = buf[m & 1];
-        double *Y = buf[(m + 1) & 1];
-        for (int t = wave; t < G::TILES; t += kTensorThreads / 64) {
+        d4 acc[G::TPW];
+#pragma unroll
+        for (int u = 0; u < G::TPW; ++u) {
+            const int t = wave + 4 * u;  // wave-uniform: every lane runs the MFMA
+            acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+            if (t >= G::TILES) continue;
             const int Lg = t * 16 + (lane & 15);  // this lane's line (B column, D column)
             const bool lok = Lg < nlines;
             const int g = lok ? Lg / G::LINES : 0;
             const int L = lok ? Lg % G::LINES : 0;
-            d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int s = 0; s < G::KS; ++s) {
                 const int k = 4 * s + kq;
-                const double b = (lok && k < N) ? X[tpad<N, DIM>(g, tnode<N, DIM>(L, k, m))] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b, acc, 0, 0, 0);
+                const double b = (lok && k < N) ? buf[tpad<N, DIM>(g, tnode<N, DIM>(L, k, m))] : 0.0;
+                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b, acc[u], 0, 0, 0);
             }
-            // D[q][line] in register r, q = 4 r + lane / 16
+        }
+        if (m < DIM - 1) __syncthreads();  // every read of this pass is done
+        // D[q][line] in register r, q = 4 r + lane / 16
+#pragma unroll
+        for (int u = 0; u < G::TPW; ++u) {
+            const int t = wave + 4 * u;
+            if (t >= G::TILES) continue;
+            const int Lg = t * 16 + (lane & 15);
+            if (Lg >= nlines) continue;
+            const int g = Lg / G::LINES;
+            const int L = Lg % G::LINES;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int q = 4 * r + kq;
-                if (!lok || q >= N) continue;
+                if (q >= N) continue;
                 const int nd = tnode<N, DIM>(L, q, m);
                 if (m == DIM - 1)
-                    out[(s0 + g) * G::NODES + nd] = acc[r];
+                    out[(s0 + g) * G::NODES + nd] = acc[u][r];
                 else
-                    Y[tpad<N, DIM>(g, nd)] = acc[r];
+                    buf[tpad<N, DIM>(g, nd)] = acc[u][r];
             }
         }
-        if (m < DIM - 1) __syncthreads();
+        if (m < DIM - 1) __syncthreads();  // the pass's results are in place
     }
 }
 
