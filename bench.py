@@ -160,6 +160,42 @@ def serving_leg(torch, W, sfhad, n_req: int, fp64_dof_per_s: float) -> dict:
     return out
 
 
+def fig1_leg(torch, sfhad, W, stream) -> dict:
+    """The Results section's Figure 1 experiment on the GPU: 3D, product flux
+    C_ij = c_i c_j with c ~ U[1e-8, 30], unweighted D (Q = D, w = 1); time per
+    element of the sum-factorized and the dense kernels against n, and the
+    log-log slopes (the paper: 4 and 6).  Element counts keep the device
+    saturated: about 2^26 / n^4 (sum-factorized) and 2^32 / n^6 (dense)."""
+    ns = [4, 6, 8, 10, 12, 14, 16]
+    t_sf, t_dense = [], []
+    for n in ns:
+        x, w, Q = sfhad.operator_1d(n, "gl")
+        D = Q / w[:, None]
+        ones = np.ones(n)
+        Es = max(4096, int(2 ** 26 / n ** 4))
+        Ed = max(2048, int(2 ** 32 / n ** 6))
+        res = []
+        for E, dense in ((Es, False), (Ed, True)):
+            c = torch.from_numpy(W.scalar_state(E, n, 3, seed=n, lo=1e-8, hi=30.0)).cuda()
+            o = torch.empty_like(c)
+            fn = sfhad.dense_volume if dense else sfhad.volume
+
+            def step():
+                fn(c, n, 3, "product", out=o, stream=stream, Q=D, w=ones)
+
+            step()
+            _, k = timed_launches(torch, step, 3, stream)
+            res.append(k * 1e3 / E)
+            del c, o
+        t_sf.append(res[0]); t_dense.append(res[1])
+    sel = [i for i, n in enumerate(ns) if n >= 6]
+    lx = np.log([ns[i] for i in sel])
+    return {"n": ns, "sf_us_per_element": t_sf, "dense_us_per_element": t_dense,
+            "sf_slope": float(np.polyfit(lx, np.log([t_sf[i] for i in sel]), 1)[0]),
+            "dense_slope": float(np.polyfit(lx, np.log([t_dense[i] for i in sel]), 1)[0]),
+            "fit": "least squares over n = 6..16", "paper_slopes": {"sf": 4, "dense": 6}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -361,6 +397,13 @@ def main() -> int:
                                          "dof_per_s": w2.dof / (per_launch * 1e-3),
                                          "elem_evals_per_s": w2.E / (per_launch * 1e-3)}
         log(f"[bench] n=4 E=4096 in a graph: {per_launch * 1e3:.2f} us/launch")
+
+    if not args.no_extras:
+        f1 = fig1_leg(torch, sfhad, W, stream)
+        result["figure1_gpu"] = f1
+        log(f"[bench] Figure 1 on the GPU: slopes sf {f1['sf_slope']:.2f} dense {f1['dense_slope']:.2f} "
+            f"(us/element sf {['%.3g' % t for t in f1['sf_us_per_element']]}, "
+            f"dense {['%.3g' % t for t in f1['dense_us_per_element']]})")
 
     if not args.no_extras and not args.no_serving:
         result["serving"] = serving_leg(torch, W, sfhad, args.serve_requests, value)

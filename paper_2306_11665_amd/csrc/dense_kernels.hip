@@ -23,9 +23,13 @@ struct DenseGeom {
 
 template <int N, int DIM, class P>
 __global__ void __launch_bounds__((DenseGeom<N, DIM>::THREADS))
-dense_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int64_t E,
-                    const OpArg<N> op, double gamma) {
+dense_volume_kernel(const VolArgs<N>) {
     using G = DenseGeom<N, DIM>;
+    const auto A = kernel_args<VolArgs<N>>();
+    const double *__restrict__ u = A->u;
+    double *__restrict__ out = A->out;
+    const int64_t E = A->E;
+    const double gamma = A->gamma;
     constexpr int NODES = G::NODES;
     __shared__ double lds[P::NS * NODES];
     __shared__ double sQ[N * N];
@@ -36,8 +40,8 @@ dense_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int6
     const size_t vstride = (size_t)E * NODES;
     const size_t gbase = (size_t)e * NODES;
 
-    for (int i = tid; i < N * N; i += G::THREADS) sQ[i] = op.Q[i];
-    for (int i = tid; i < N; i += G::THREADS) sw[i] = op.w[i];
+    for (int i = tid; i < N * N; i += G::THREADS) sQ[i] = A->op.Q[i];
+    for (int i = tid; i < N; i += G::THREADS) sw[i] = A->op.w[i];
     constexpr int NREF = P::NREF > 0 ? P::NREF : 1;
     __shared__ double sref[NREF];
     if (P::NREF > 0) {
@@ -92,10 +96,14 @@ dense_volume_kernel(const double *__restrict__ u, double *__restrict__ out, int6
 }
 
 template <int N>
-OpArg<N> make_dense_op(const Operator1D &op) {
-    OpArg<N> a;
-    for (int i = 0; i < N * N; ++i) a.Q[i] = op.Q[i];
-    for (int i = 0; i < N; ++i) a.w[i] = op.w[i];
+VolArgs<N> make_dense_args(const VolumeRequest &r) {
+    VolArgs<N> a;
+    a.u = r.u;
+    a.out = r.out;
+    a.E = r.E;
+    a.gamma = r.gamma;
+    for (int i = 0; i < N * N; ++i) a.op.Q[i] = r.op.Q[i];
+    for (int i = 0; i < N; ++i) a.op.w[i] = r.op.w[i];
     return a;
 }
 
@@ -107,7 +115,7 @@ int launch_dense(const VolumeRequest &r) {
         return SF_ERR_UNSUPPORTED;
     }
     hipLaunchKernelGGL((dense_volume_kernel<N, DIM, P>), dim3((unsigned)r.E), dim3(G::THREADS), 0,
-                       r.stream, r.u, r.out, r.E, make_dense_op<N>(r.op), r.gamma);
+                       r.stream, make_dense_args<N>(r));
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) {
         set_error(std::string("dense_volume_kernel launch: ") + hipGetErrorString(err));

@@ -31,6 +31,31 @@ struct OpArg {
     double w[N];
 };
 
+// The whole argument block of a standalone volume kernel, its only
+// parameter.  Kernels read it through the kernel-argument segment pointer
+// (constant address space, so the reads are scalar loads): naming the
+// by-value parameter directly makes clang copy it into private memory, and
+// once the block is too large to split into registers (n >= 11) every
+// operator read would be a scratch access.
+template <int N>
+struct VolArgs {
+    const double *u;
+    double *out;
+    int64_t E;
+    double gamma;
+    OpArg<N> op;
+};
+
+template <class T>
+using kernarg_ptr = const __attribute__((address_space(4))) T *;
+
+// The argument block of the running kernel (its first and only parameter
+// starts at offset 0 of the segment).
+template <class T>
+__device__ __forceinline__ kernarg_ptr<T> kernel_args() {
+    return (kernarg_ptr<T>)__builtin_amdgcn_kernarg_segment_ptr();
+}
+
 template <int N, int DIM>
 struct Geom {
     static constexpr int LINES = DIM == 3 ? N * N : N;       // lines per direction per element

@@ -168,7 +168,7 @@ def test_scalar_all_n(torch_dev, sf, orc, flux, d, n):
 
 @pytest.mark.parametrize("flux,d,n", [("euler", 3, 2), ("euler", 3, 4), ("euler", 3, 5), ("euler", 3, 8),
                                       ("burgers", 2, 4), ("burgers", 3, 6), ("product", 3, 8),
-                                      ("product", 2, 16)])
+                                      ("product", 2, 16), ("product", 3, 12), ("product", 3, 16)])
 def test_dense_gpu_path(torch_dev, sf, orc, flux, d, n):
     E = 3
     u = state(flux, E, n, d, seed=300 + n)
