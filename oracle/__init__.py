@@ -65,6 +65,9 @@ def lib():
         L.oracle_basis_sparse.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ip, ip, dp]
         L.oracle_basis_1d.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
         L.oracle_tensor_apply.argtypes = [dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
+        L.oracle_lagrange_endpoints.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
+        L.oracle_surface.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     dp, dp, dp, ctypes.c_double, dp, dp]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         L.oracle_set_num_threads.restype = None
@@ -198,6 +201,38 @@ def tensor_apply(u, n: int, d: int, M) -> np.ndarray:
     if lib().oracle_tensor_apply(_dp(u), u.shape[1], n, d, u.shape[0], _dp(M), _dp(out)) != 0:
         raise ValueError("oracle rejected arguments")
     return out
+
+
+def lagrange_endpoints(n: int, kind: str = "gl"):
+    """(lm, lp): the Lagrange basis of the nodes at -1 and +1."""
+    lm = np.zeros(n); lp = np.zeros(n)
+    if lib().oracle_lagrange_endpoints(n, NODES[kind], _dp(lm), _dp(lp)) != 0:
+        raise ValueError("bad arguments")
+    return lm, lp
+
+
+def surface(u, uf, n: int, d: int, flux_kind: str, w=None, lm=None, lp=None, nodes_kind="gl", gamma=1.4):
+    """The surface term by its definition: (y_vol, y_face) for volume states
+    u (nvar, E, n^d) and facet states uf (nvar, E, 2d, n^(d-1))."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    uf = np.ascontiguousarray(uf, dtype=np.float64)
+    nv = NVAR[flux_kind]
+    E = u.shape[1]
+    if u.shape != (nv, E, n ** d) or uf.shape != (nv, E, 2 * d, n ** (d - 1)):
+        raise ValueError("shape mismatch")
+    if w is None:
+        _, w = nodes(n, nodes_kind)
+    if lm is None or lp is None:
+        lm0, lp0 = lagrange_endpoints(n, nodes_kind)
+        lm = lm0 if lm is None else lm
+        lp = lp0 if lp is None else lp
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    lm = np.ascontiguousarray(lm, dtype=np.float64); lp = np.ascontiguousarray(lp, dtype=np.float64)
+    yv = np.zeros_like(u); yf = np.zeros_like(uf)
+    if lib().oracle_surface(_dp(u), _dp(uf), E, n, d, FLUX[flux_kind], _dp(w), _dp(lm), _dp(lp), gamma,
+                            _dp(yv), _dp(yf)) != 0:
+        raise ValueError("oracle rejected arguments")
+    return yv, yf
 
 
 def num_threads() -> int:

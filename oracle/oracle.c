@@ -24,6 +24,9 @@
  *     oracle_sf_volume below restate those steps for d = 3 (and the d = 2
  *     form that follows from Eq. (2)).
  *
+ *   - The Remark after Eq. (5): the same Hadamard product with alpha = 0 and
+ *     facet cubature nodes, the surface terms.  oracle_lagrange_endpoints and
+ *     oracle_surface give its plain definition (see there).
  *   - Eq. (6) and the proof of Theorem 1: a polynomial basis chi evaluated
  *     on the nodes, its projection Pi with Pi chi = I, and the basis
  *     transformation applied direction by direction.  oracle_basis_1d and
@@ -523,6 +526,116 @@ int oracle_tensor_apply(const double *in, long E, int n, int d, int nvar, const 
         }
     }
     free(K);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Surface Hadamard product (the Remark after Eq. (5): alpha = 0, facet      */
+/* cubature nodes)                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Lagrange basis of the n nodes at the reference-interval ends, by the
+ * textbook product l_k(x) = prod_{j != k} (x - x_j) / (x_k - x_j):
+ * lm[k] = l_k(-1), lp[k] = l_k(+1). */
+int oracle_lagrange_endpoints(int n, int kind, double *lm, double *lp)
+{
+    if (n < 1 || n > 64) return -1;
+    double x[64], w[64];
+    if (oracle_nodes(n, kind, x, w) != 0) return -1;
+    for (int k = 0; k < n; ++k) {
+        double a = 1.0, b = 1.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == k) continue;
+            a *= (-1.0 - x[j]) / (x[k] - x[j]);
+            b *= (1.0 - x[j]) / (x[k] - x[j]);
+        }
+        lm[k] = a;
+        lp[k] = b;
+    }
+    return 0;
+}
+
+/* The surface term by its definition.  Face f = 2m + s of an element is the
+ * facet xi_m = -1 (s = 0) or +1 (s = 1); its cubature nodes are the tensor
+ * product of the nodes in the other directions (n^(d-1) of them, index t
+ * with the remaining directions in increasing order, first fastest).  With
+ * alpha = 0 the basis operator of Eq. (6) restricted to the facet is the
+ * interpolation to it, weighted by the facet quadrature:
+ *     B_f = (factor per direction, slowest first)  l_s^T in position m,
+ *           W = diag(w) in every other position,
+ * an n^(d-1) x n^d matrix built here as an explicit Kronecker product.  With
+ * C_f[t][v] = f_m(u_face[t], u_vol[v]) over ALL facet-volume pairs:
+ *     y_face_f = (B_f o C_f) 1          (row sums, one per facet node)
+ *     y_vol   += (B_f o C_f)^T 1        (column sums, every face)
+ * Layouts: u_vol / y_vol as the volume term; u_face / y_face
+ * [v][e][f][t] with 2d faces of n^(d-1) nodes.  w, lm, lp: the 1D weights and
+ * the Lagrange end values (any override may be passed). */
+int oracle_surface(const double *u, const double *uf, long E, int n, int d, int flux,
+                   const double *w, const double *lm, const double *lp, double gamma,
+                   double *yv, double *yf)
+{
+    if (!u || !uf || !yv || !yf || !w || !lm || !lp || E < 0 || n < 1 || d < 2 || d > 3) return -1;
+    int N = 1;
+    for (int k = 0; k < d; ++k) N *= n;
+    const int T = N / n, NF = 2 * d;
+    const int nv = flux_nvar(flux);
+    double *Wm = (double *)calloc((size_t)n * n, sizeof(double));
+    for (int i = 0; i < n; ++i) Wm[i * n + i] = w[i];
+    double *B = (double *)malloc(sizeof(double) * (size_t)NF * T * N);
+    double *cur = (double *)malloc(sizeof(double) * (size_t)T * N);
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)T * N);
+    for (int f = 0; f < NF; ++f) {
+        const int m = f / 2;
+        const double *ls = (f % 2) ? lp : lm;
+        /* slowest factor first: position d-1 (z) down to 0 (x) */
+        int rows = (d - 1 == m) ? 1 : n, cols = n;
+        if (d - 1 == m) memcpy(cur, ls, sizeof(double) * n);
+        else memcpy(cur, Wm, sizeof(double) * n * n);
+        for (int k = d - 2; k >= 0; --k) {
+            if (k == m) {
+                kron(cur, rows, cols, ls, 1, n, tmp);
+                cols *= n;
+            } else {
+                kron(cur, rows, cols, Wm, n, n, tmp);
+                rows *= n;
+                cols *= n;
+            }
+            memcpy(cur, tmp, sizeof(double) * (size_t)rows * cols);
+        }
+        memcpy(B + (size_t)f * T * N, cur, sizeof(double) * (size_t)T * N);
+    }
+    free(cur); free(tmp); free(Wm);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long e = 0; e < E; ++e) {
+        double *ue = (double *)malloc(sizeof(double) * (size_t)N * nv);
+        double *ye = (double *)calloc((size_t)N * nv, sizeof(double));
+        double ufn[5], F[5];
+        for (int i = 0; i < N; ++i)
+            for (int v = 0; v < nv; ++v) ue[i * nv + v] = u[(size_t)v * E * N + (size_t)e * N + i];
+        for (int f = 0; f < NF; ++f) {
+            const int m = f / 2;
+            const double *Bf = B + (size_t)f * T * N;
+            for (int t = 0; t < T; ++t) {
+                double acc[5] = {0, 0, 0, 0, 0};
+                for (int v = 0; v < nv; ++v)
+                    ufn[v] = uf[(size_t)v * E * NF * T + ((size_t)e * NF + f) * T + t];
+                for (int j = 0; j < N; ++j) {
+                    oracle_flux(flux, ufn, ue + j * nv, m, gamma, F);
+                    const double b = Bf[(size_t)t * N + j];
+                    for (int v = 0; v < nv; ++v) {
+                        acc[v] += b * F[v];
+                        ye[j * nv + v] += b * F[v];
+                    }
+                }
+                for (int v = 0; v < nv; ++v)
+                    yf[(size_t)v * E * NF * T + ((size_t)e * NF + f) * T + t] = acc[v];
+            }
+        }
+        for (int i = 0; i < N; ++i)
+            for (int v = 0; v < nv; ++v) yv[(size_t)v * E * N + (size_t)e * N + i] = ye[i * nv + v];
+        free(ue); free(ye);
+    }
+    free(B);
     return 0;
 }
 
