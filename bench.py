@@ -372,6 +372,38 @@ def main() -> int:
             f"{tbytes / (kt * 1e-3) / 1e9:.0f} GB/s ({tbytes / (kt * 1e-3) / 1e9 / PEAK_HBM_GBS:.2f} of HBM peak)")
         del ti
 
+        # surface term (facet states drawn like the volume states) alone and
+        # fused with the volume term, same mesh
+        rng = np.random.default_rng(91)
+        kf = 6 * n * n
+        rho = rng.uniform(0.5, 1.5, (E, kf)); vel = rng.uniform(-0.5, 0.5, (3, E, kf))
+        pr = rng.uniform(0.5, 1.5, (E, kf))
+        uf = torch.from_numpy(W.primitives_to_conserved(rho, vel, pr).reshape(5, E, 6, n * n).copy()).cuda()
+        del rho, vel, pr
+        yv_s = torch.empty_like(ut); yf_s = torch.empty_like(uf)
+
+        def steps_():
+            sfhad.surface(ut, uf, n, 3, "euler", stream=stream, y_vol=yv_s, y_face=yf_s)
+
+        def stepvs():
+            sfhad.surface(ut, uf, n, 3, "euler", stream=stream, y_vol=yv_s, y_face=yf_s, with_volume=True)
+
+        for _ in range(args.warmup):
+            steps_(); stepvs()
+        _, ks = timed_launches(torch, steps_, args.steps, stream)
+        _, kvs = timed_launches(torch, stepvs, args.steps, stream)
+        result["surface"] = {
+            "what": "sf_hadamard_surface (2 d n^d facet-volume flux pairs per element) and "
+                    "sf_hadamard_volume_surface (both terms, one pass), n = 8, 32768 elements",
+            "surface_ms": ks, "volume_plus_surface_fused_ms": kvs,
+            "volume_then_surface_ms": kern_ms + ks,
+            "fused_dof_per_s": dof / (kvs * 1e-3),
+            "surface_flux_pairs_per_element": 6 * n ** 3,
+        }
+        log(f"[bench] surface: {ks * 1e3:.1f} us; volume+surface fused {kvs * 1e3:.1f} us "
+            f"(separate {1e3 * (kern_ms + ks):.1f} us)")
+        del uf, yv_s, yf_s
+
         # n = 4 workload: 100 launches captured in one HIP graph
         w2 = W.WORKLOADS["euler3d_n4_gl_e4096"]
         u2 = torch.from_numpy(w2.state()).cuda()

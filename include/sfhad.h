@@ -122,6 +122,42 @@ int sf_hadamard_volume_ex(const double *u_nodes, int64_t elem_count, int n, int 
 int dense_hadamard_volume_ex(const double *u_nodes, int64_t elem_count, int n, int d,
                              int flux_kind, double *out, const sf_opts *opts);
 
+/* ---------------------------------------------------------------------
+ * Surface term (the Remark after Eq. (5): the same Hadamard product with
+ * alpha = 0 on the facet cubature nodes).  Face f = 2m + s of an element is
+ * the facet xi_m = -1 (s = 0) or +1 (s = 1); its n^(d-1) cubature nodes are
+ * the tensor product of the nodes in the other directions, index t with the
+ * remaining directions in increasing order, first fastest (for d = 3:
+ * m = 0: t = iy + n iz; m = 1: t = ix + n iz; m = 2: t = ix + n iy).  The
+ * facet operator is the quadrature-weighted interpolation to the facet,
+ *     B_f = l_s^T in direction m, W = diag(w) in the others
+ * (l_s[k] = l_k(-1) or l_k(+1), the Lagrange basis of the nodes at the
+ * interval end), so with C_f[t][v] = f_m(u_face[t], u_vol[v]):
+ *     y_face_f = (B_f o C_f) 1        y_vol = sum_f (B_f o C_f)^T 1.
+ * Only the n volume nodes on the line through a facet node have a nonzero
+ * coefficient: 2 d n^d flux evaluations per element.
+ *   u_vol, y_vol   device, nvar * E * n^d doubles, the volume layout
+ *   u_face, y_face device, nvar * E * 2d * n^(d-1) doubles,
+ *                  [v][e][f][t]; the facet states (a trace, an interface
+ *                  state -- any admissible state)
+ *   y_vol and y_face are fully overwritten and must not overlap each other
+ *   or an input (SF_ERR_ARG).  opts: node_kind, gamma, stream and the w
+ *   override as for the volume term (Q is not used; the facet interpolation
+ *   always uses node_kind's end values); FP64 only (SF_ERR_UNSUPPORTED for
+ *   the FP32-split precision).  Shapes as sf_hadamard_volume. */
+int sf_hadamard_surface(const double *u_vol, const double *u_face, int64_t elem_count, int n, int d,
+                        int flux_kind, double *y_vol, double *y_face, const sf_opts *opts);
+
+/* The volume and surface terms in one pass: y_vol = sum_m (A_m o F_m) 1 +
+ * sum_f (B_f o C_f)^T 1 and y_face as above (arguments as
+ * sf_hadamard_surface; y_vol holds the sum of the two terms). */
+int sf_hadamard_volume_surface(const double *u_vol, const double *u_face, int64_t elem_count, int n, int d,
+                               int flux_kind, double *y_vol, double *y_face, const sf_opts *opts);
+
+/* The Lagrange basis of the n nodes at the interval ends (host, FP64):
+ * lm[k] = l_k(-1), lp[k] = l_k(+1); either may be NULL.  No GPU needed. */
+int sf_surface_operator_1d(int n, int node_kind, double *lm_host, double *lp_host);
+
 /* The 1D operator the kernels use (FP64, on [-1, 1]): nodes x, weights w and
  * Q = diag(w) D, row-major n x n (Eq. (5)).  Host buffers of n, n and n*n
  * doubles; any of them may be NULL.  No GPU needed. */

@@ -87,6 +87,39 @@ int validate(const double *u, int64_t E, int n, int d, int flux, double *out, co
     return SF_OK;
 }
 
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    const char *x = reinterpret_cast<const char *>(a), *y = reinterpret_cast<const char *>(b);
+    return x < y + nb && y < x + na;
+}
+
+// The surface term (mode kModeSurface) or volume + surface (kModeVolumeSurface).
+int run_surface(const double *u, const double *uf, int64_t E, int n, int d, int flux, double *yv, double *yf,
+                const sf_opts *opts, int mode) {
+    VolumeRequest r;
+    int st = validate(u, E, n, d, flux, yv, opts, false, r);
+    if (st != SF_OK || E == 0) return st;
+    if (r.precision != SF_PREC_FP64) return fail(SF_ERR_UNSUPPORTED, "the surface term is built in FP64 only");
+    if (!uf || !yf) return fail(SF_ERR_ARG, "null u_face or y_face");
+    const int nv = flux_nvar(flux);
+    const size_t vbytes = (size_t)(ipow(n, d) * nv * E) * sizeof(double);
+    const size_t fbytes = (size_t)(2 * d * ipow(n, d - 1) * nv * E) * sizeof(double);
+    if (overlaps(yf, fbytes, uf, fbytes) || overlaps(yf, fbytes, u, vbytes) || overlaps(yf, fbytes, yv, vbytes) ||
+        overlaps(yv, vbytes, uf, fbytes))
+        return fail(SF_ERR_ARG, "outputs overlap each other or an input");
+    // the facet interpolation always uses the node kind's own end values
+    Operator1D base;
+    if (!get_operator(n, r.op.node_kind, base))
+        return fail(SF_ERR_UNSUPPORTED, "operator construction failed");
+    for (int i = 0; i < n; ++i) {
+        r.op.lm[i] = base.lm[i];
+        r.op.lp[i] = base.lp[i];
+    }
+    r.uf = uf;
+    r.yf = yf;
+    r.mode = mode;
+    return launch_sf_surface(r);
+}
+
 int run(const double *u, int64_t E, int n, int d, int flux, double *out, const sf_opts *opts,
         bool dense) {
     VolumeRequest r;
@@ -129,6 +162,28 @@ int sf_hadamard_volume_ex(const double *u, int64_t E, int n, int d, int flux, do
 int dense_hadamard_volume_ex(const double *u, int64_t E, int n, int d, int flux, double *out,
                              const sf_opts *opts) {
     return run(u, E, n, d, flux, out, opts, true);
+}
+
+int sf_hadamard_surface(const double *u, const double *uf, int64_t E, int n, int d, int flux, double *yv,
+                        double *yf, const sf_opts *opts) {
+    return run_surface(u, uf, E, n, d, flux, yv, yf, opts, kModeSurface);
+}
+
+int sf_hadamard_volume_surface(const double *u, const double *uf, int64_t E, int n, int d, int flux, double *yv,
+                               double *yf, const sf_opts *opts) {
+    return run_surface(u, uf, E, n, d, flux, yv, yf, opts, kModeVolumeSurface);
+}
+
+int sf_surface_operator_1d(int n, int node_kind, double *lm, double *lp) {
+    if (n < 1) return fail(SF_ERR_ARG, "n must be >= 1");
+    if (node_kind != SF_NODES_GAUSS_LEGENDRE && node_kind != SF_NODES_GAUSS_LOBATTO)
+        return fail(SF_ERR_ARG, "unknown node_kind");
+    if (n < SF_MIN_N || n > SF_MAX_N) return fail(SF_ERR_UNSUPPORTED, "n outside [2, 16]");
+    Operator1D op;
+    if (!get_operator(n, node_kind, op)) return fail(SF_ERR_UNSUPPORTED, "operator construction failed");
+    if (lm) std::memcpy(lm, op.lm, sizeof(double) * n);
+    if (lp) std::memcpy(lp, op.lp, sizeof(double) * n);
+    return SF_OK;
 }
 
 int sf_operator_1d(int n, int node_kind, double *x, double *w, double *Q) {

@@ -142,6 +142,30 @@ bool build_operator(int n, int node_kind, Operator1D &op) {
     derivative_matrix(n, op.x, D);
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) op.Q[i * n + j] = op.w[i] * D[i * n + j];
+    // Lagrange basis at x = -1 and +1, barycentric form
+    // l_k(x) = (lambda_k / (x - x_k)) / sum_j lambda_j / (x - x_j); a node on the
+    // end (Gauss-Lobatto) gives the unit vector exactly
+    double lam[kMaxN];
+    for (int j = 0; j < n; ++j) {
+        double p = 1.0;
+        for (int k = 0; k < n; ++k)
+            if (k != j) p *= op.x[j] - op.x[k];
+        lam[j] = 1.0 / p;
+    }
+    for (int side = 0; side < 2; ++side) {
+        const double X = side ? 1.0 : -1.0;
+        double *l = side ? op.lp : op.lm;
+        int hit = -1;
+        for (int k = 0; k < n; ++k)
+            if (op.x[k] == X) hit = k;
+        if (hit >= 0) {
+            for (int k = 0; k < n; ++k) l[k] = k == hit ? 1.0 : 0.0;
+            continue;
+        }
+        double den = 0.0;
+        for (int j = 0; j < n; ++j) den += lam[j] / (X - op.x[j]);
+        for (int k = 0; k < n; ++k) l[k] = (lam[k] / (X - op.x[k])) / den;
+    }
     return true;
 }
 

@@ -12,13 +12,17 @@ namespace sfhad {
 
 constexpr int kMaxN = 16;
 
-// The 1D operator of Eq. (5): nodes, weights and Q = diag(w) D (row-major).
+// The 1D operator of Eq. (5): nodes, weights and Q = diag(w) D (row-major),
+// and the Lagrange basis at the interval ends, lm[k] = l_k(-1),
+// lp[k] = l_k(+1) (the facet interpolation of the surface term).
 struct Operator1D {
     int n = 0;
     int node_kind = -1;
     double x[kMaxN];
     double w[kMaxN];
     double Q[kMaxN * kMaxN];
+    double lm[kMaxN];
+    double lp[kMaxN];
 };
 
 bool build_operator(int n, int node_kind, Operator1D &op);
@@ -39,12 +43,19 @@ struct VolumeRequest {
     double gamma = 1.4;
     hipStream_t stream = nullptr;
     Operator1D op;
+    // surface term (the Remark after Eq. (5)): facet states and outputs,
+    // [v][e][2d faces][n^(d-1)]; mode selects what a launch computes
+    const double *uf = nullptr;
+    double *yf = nullptr;
+    int mode = 0;
 };
+enum { kModeVolume = 0, kModeSurface = 1, kModeVolumeSurface = 2 };
 
 // Kernel launchers (volume_kernels.hip / dense_kernels.hip).  They return
 // SF_OK, SF_ERR_UNSUPPORTED for a shape that is not instantiated, or
 // SF_ERR_HIP when the launch fails.
 int launch_sf_volume(const VolumeRequest &r);
+int launch_sf_surface(const VolumeRequest &r);  // kModeSurface or kModeVolumeSurface
 int launch_dense_volume(const VolumeRequest &r);
 
 // ---------------------------------------------------------------------------

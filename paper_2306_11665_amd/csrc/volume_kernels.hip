@@ -123,11 +123,25 @@ struct TableOp {
     __device__ double w(int i) const { return W[i]; }
 };
 
+// The per-line work of a block.  VolumeWork is a2..a5 (every pair of the
+// line); SurfaceWork is the facet part of the surface term (below);
+// VolumeSurfaceWork does both into the same line sums.
+struct VolumeWork {
+    template <int M, int N, class P, class Op, class R>
+    __device__ __forceinline__ void lines(const R *le, int AS, int pbase, int pstride, const Op &op,
+                                          const typename P::Consts &K, double gamma, R (&t)[N][P::NV], int64_t,
+                                          int, double, const double *) const {
+        line_pairs<N, P, M>(le, AS, pbase, pstride, op, K, gamma, t);
+    }
+};
+
 // One block of EPB elements starting at element e0 of an E-element mesh:
-// steps a1..a6.  lds holds SfLayout::LDS_D doubles, sref SfLayout::REF_D.
-template <int N, int DIM, class P, class Op>
+// steps a1..a6 with the line work of `work`.  lds holds SfLayout::LDS_D
+// doubles, sref SfLayout::REF_D.
+template <int N, int DIM, class P, class Op, class Work = VolumeWork>
 __device__ __forceinline__ void sf_block(const double *__restrict__ u, double *__restrict__ out, int64_t E,
-                                         int64_t e0, const Op &op, double gamma, double *lds, double *sref) {
+                                         int64_t e0, const Op &op, double gamma, double *lds, double *sref,
+                                         const Work &work = Work{}) {
     using G = Geom<N, DIM>;
     using L = SfLayout<N, DIM, P>;
     using R = typename P::Real;
@@ -199,12 +213,14 @@ __device__ __forceinline__ void sf_block(const double *__restrict__ u, double *_
     if (active) {
         // m is uniform per wave; one instantiation per direction turns the
         // rotated array offsets into immediates
+        const int64_t e = e0 + el;
+        const double *ref = sref + el * NREF;
         if (m == 0)
-            line_pairs<N, P, 0>(le, AS, pbase, pstride, op, K, gamma, t);
+            work.template lines<0, N, P>(le, AS, pbase, pstride, op, K, gamma, t, e, line, wperp, ref);
         else if (DIM == 2 || m == 1)
-            line_pairs<N, P, 1>(le, AS, pbase, pstride, op, K, gamma, t);
+            work.template lines<1, N, P>(le, AS, pbase, pstride, op, K, gamma, t, e, line, wperp, ref);
         else
-            line_pairs<N, P, 2>(le, AS, pbase, pstride, op, K, gamma, t);
+            work.template lines<2, N, P>(le, AS, pbase, pstride, op, K, gamma, t, e, line, wperp, ref);
     }
     __syncthreads();  // every lane is done reading the staged inputs
 
@@ -283,6 +299,147 @@ int launch_sf(const VolumeRequest &r) {
         return SF_ERR_HIP;
     }
     return SF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Surface term (the Remark after Eq. (5): the Hadamard product with alpha = 0
+// on the facet cubature nodes).  The facet operator of face (m, s) is the
+// quadrature-weighted interpolation to xi_m = -1 (s = 0) or +1 (s = 1):
+// l_s^T in direction m, W in the others.  Its nonzeros pair each facet node
+// with the n volume nodes of the line through it, so the lane that owns line
+// L of direction m also owns the two facet nodes t = L of faces (m, 0) and
+// (m, 1).  For each it stages the facet state like a volume node (same
+// element reference, so log differences stay accurate), evaluates the flux
+// with the line's n volume nodes, and accumulates
+//     y_face[t] = w_perp sum_k l_s[k] f_m(u_face[t], u_k)   (stored here)
+//     t_k      += l_s[k] f_m(u_face[t], u_k)                (line sums; a6
+//                                                          applies w_perp)
+// 2 d n^d flux evaluations per element.  With VOLUME the line's pairs (a2..a5)
+// go into the same line sums first: volume and surface terms in one pass.
+template <int N, int DIM, bool VOLUME>
+struct SurfaceWork {
+    const double *__restrict__ uf;
+    double *__restrict__ yf;
+    int64_t E;
+    kernarg_ptr<double> ell;  // l_s[k] at ell[s * N + k]
+
+    template <int M, int NN, class P, class Op, class R>
+    __device__ __forceinline__ void lines(const R *le, int AS, int pbase, int pstride, const Op &op,
+                                          const typename P::Consts &K, double gamma, R (&t)[NN][P::NV],
+                                          int64_t e, int line, double wperp, const double *ref) const {
+        if constexpr (VOLUME) line_pairs<NN, P, M>(le, AS, pbase, pstride, op, K, gamma, t);
+        constexpr int T = DIM == 3 ? NN * NN : NN;  // facet nodes per face
+        constexpr int NF = 2 * DIM;
+        const size_t fstride = (size_t)E * NF * T;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const size_t fidx = ((size_t)e * NF + 2 * M + s) * T + line;
+            double uc[P::NV];
+#pragma unroll
+            for (int v = 0; v < P::NV; ++v) uc[v] = uf[v * fstride + fidx];
+            R sa[P::NS];
+            P::stage(uc, ref, gamma, sa);
+            const typename P::Node A = P::load(sa, 1, 0, M);
+            R yfa[P::NV];
+#pragma unroll
+            for (int k = 0; k < P::NV; ++k) yfa[k] = (R)0;
+#pragma unroll
+            for (int c = 0; c < NN; ++c) {
+                const typename P::Node C = P::load_partner(le, AS, pin(pbase + c * pstride), M);
+                R F[P::NV];
+                P::pair(A, C, K, F);
+                const R l = (R)ell[s * NN + c];
+#pragma unroll
+                for (int k = 0; k < P::NV; ++k) {
+                    yfa[k] = l * F[k] + yfa[k];
+                    t[c][k] = l * F[k] + t[c][k];
+                }
+#pragma unroll
+                for (int k = 0; k < P::NV; ++k) {
+                    yfa[k] = pin(yfa[k]);
+                    t[c][k] = pin(t[c][k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < P::NV; ++k) yf[P::out_array(k, M) * fstride + fidx] = (double)yfa[k] * wperp;
+        }
+    }
+};
+
+template <int N>
+struct SurfArgs {
+    const double *u;
+    const double *uf;
+    double *yv;
+    double *yf;
+    int64_t E;
+    double gamma;
+    OpArg<N> op;
+    double ell[2 * N];
+};
+
+// at least 3 waves per SIMD (at most 168 VGPRs): the fused form would
+// otherwise take 188 at n = 8 and run 2
+template <int N, int DIM, class P, bool VOLUME>
+__global__ void __launch_bounds__((Geom<N, DIM>::THREADS), 3)
+sf_surface_kernel(const SurfArgs<N>) {
+    using L = SfLayout<N, DIM, P>;
+    __shared__ double lds[L::LDS_D];
+    __shared__ double sref[L::REF_D];
+    const auto A = kernel_args<SurfArgs<N>>();
+    sf_block<N, DIM, P>(A->u, A->yv, A->E, (int64_t)blockIdx.x * Geom<N, DIM>::EPB, KernargOp<N>{&A->op},
+                        A->gamma, lds, sref, SurfaceWork<N, DIM, VOLUME>{A->uf, A->yf, A->E, &A->ell[0]});
+}
+
+template <int N, int DIM, class P>
+int launch_surface(const VolumeRequest &r) {
+    using G = Geom<N, DIM>;
+    const int64_t blocks = (r.E + G::EPB - 1) / G::EPB;
+    if (blocks > 0x7fffffffLL) {
+        set_error("element count too large for one launch");
+        return SF_ERR_UNSUPPORTED;
+    }
+    SurfArgs<N> a;
+    a.u = r.u;
+    a.uf = r.uf;
+    a.yv = r.out;
+    a.yf = r.yf;
+    a.E = r.E;
+    a.gamma = r.gamma;
+    for (int i = 0; i < N * N; ++i) a.op.Q[i] = r.op.Q[i];
+    for (int i = 0; i < N; ++i) {
+        a.op.w[i] = r.op.w[i];
+        a.ell[i] = r.op.lm[i];
+        a.ell[N + i] = r.op.lp[i];
+    }
+    if (r.mode == kModeVolumeSurface)
+        hipLaunchKernelGGL((sf_surface_kernel<N, DIM, P, true>), dim3((unsigned)blocks), dim3(G::THREADS), 0,
+                           r.stream, a);
+    else
+        hipLaunchKernelGGL((sf_surface_kernel<N, DIM, P, false>), dim3((unsigned)blocks), dim3(G::THREADS), 0,
+                           r.stream, a);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) {
+        set_error(std::string("sf_surface_kernel launch: ") + hipGetErrorString(err));
+        return SF_ERR_HIP;
+    }
+    return SF_OK;
+}
+
+template <int DIM, class P, int NMAX>
+int dispatch_surface_n(const VolumeRequest &r) {
+    switch (r.n) {
+#define SF_CASE(NV_)                                                          \
+    case NV_:                                                                 \
+        if constexpr (NV_ <= NMAX) return launch_surface<NV_, DIM, P>(r);     \
+        break;
+        SF_CASE(2) SF_CASE(3) SF_CASE(4) SF_CASE(5) SF_CASE(6) SF_CASE(7) SF_CASE(8) SF_CASE(9)
+        SF_CASE(10) SF_CASE(11) SF_CASE(12) SF_CASE(13) SF_CASE(14) SF_CASE(15) SF_CASE(16)
+#undef SF_CASE
+        default: break;
+    }
+    set_error("n outside the built range");
+    return SF_ERR_UNSUPPORTED;
 }
 
 // Dispatch on n for a fixed (DIM, policy); n range [2, NMAX].
@@ -415,6 +572,26 @@ int launch_sf_volume(const VolumeRequest &r) {
         case SF_FLUX_EULER_CHANDRASHEKAR:
             if (r.d != 3) break;
             return dispatch_n<3, EulerFP64, SF_MAX_N_EULER>(r);
+        default: break;
+    }
+    set_error("flux / dimension combination not built");
+    return SF_ERR_UNSUPPORTED;
+}
+
+int launch_sf_surface(const VolumeRequest &r) {
+    using namespace dev;
+    if (r.precision != SF_PREC_FP64) {
+        set_error("the surface term is built in FP64 only");
+        return SF_ERR_UNSUPPORTED;
+    }
+    switch (r.flux) {
+        case SF_FLUX_BURGERS_EC:
+            return r.d == 2 ? dispatch_surface_n<2, ScalarFlux<0>, 16>(r) : dispatch_surface_n<3, ScalarFlux<0>, 16>(r);
+        case SF_FLUX_PRODUCT:
+            return r.d == 2 ? dispatch_surface_n<2, ScalarFlux<2>, 16>(r) : dispatch_surface_n<3, ScalarFlux<2>, 16>(r);
+        case SF_FLUX_EULER_CHANDRASHEKAR:
+            if (r.d != 3) break;
+            return dispatch_surface_n<3, EulerFP64, SF_MAX_N_EULER>(r);
         default: break;
     }
     set_error("flux / dimension combination not built");

@@ -82,6 +82,11 @@ def lib() -> ctypes.CDLL:
         for name in ("sf_release", "sf_mesh_unregister"):
             getattr(L, name).argtypes = [vp, i64]
             getattr(L, name).restype = ci
+        for name in ("sf_hadamard_surface", "sf_hadamard_volume_surface"):
+            getattr(L, name).argtypes = [vp, vp, i64, ci, ci, ci, vp, vp, ctypes.POINTER(SfOpts)]
+            getattr(L, name).restype = ci
+        L.sf_surface_operator_1d.argtypes = [ci, ci, _dp, _dp]
+        L.sf_surface_operator_1d.restype = ci
         L.sf_basis_1d.argtypes = [ci, ci, _dp, _dp]
         L.sf_basis_1d.restype = ci
         L.sf_tensor_apply.argtypes = [vp, i64, ci, ci, ci, _dp, vp, vp]
@@ -168,6 +173,36 @@ def volume(u, n: int, d: int, flux: str, **kw):
 def dense_volume(u, n: int, d: int, flux: str, **kw):
     """Same term over all n^(2d) pairs (dense_hadamard_volume_ex)."""
     return _call("dense_hadamard_volume_ex", u, n, d, flux, **kw)
+
+
+def surface_operator_1d(n: int, nodes: str = "gl"):
+    """(lm, lp): the Lagrange basis of the nodes at -1 and +1 (host, FP64)."""
+    lm = np.zeros(n); lp = np.zeros(n)
+    check(lib().sf_surface_operator_1d(n, NODES[nodes], lm.ctypes.data_as(_dp), lp.ctypes.data_as(_dp)),
+          "sf_surface_operator_1d")
+    return lm, lp
+
+
+def surface(u, uf, n: int, d: int, flux: str, *, with_volume=False, nodes="gl", gamma=1.4, stream=None,
+            y_vol=None, y_face=None, w=None):
+    """(y_vol, y_face) of the surface term (sf_hadamard_surface), or of the
+    volume and surface terms together (sf_hadamard_volume_surface) when
+    with_volume.  u: (nvar, E, n^d); uf: (nvar, E, 2d, n^(d-1))."""
+    import torch
+    _check_tensor(u, flux, n, d)
+    nv = NVAR[flux]
+    E = u.shape[1]
+    if (not isinstance(uf, torch.Tensor) or uf.device.type != "cuda" or uf.dtype != torch.float64
+            or not uf.is_contiguous() or tuple(uf.shape) != (nv, E, 2 * d, n ** (d - 1))):
+        raise ValueError(f"u_face must be a contiguous float64 CUDA tensor ({nv}, {E}, {2 * d}, {n ** (d - 1)})")
+    y_vol = torch.empty_like(u) if y_vol is None else y_vol
+    y_face = torch.empty_like(uf) if y_face is None else y_face
+    opts, keep = make_opts(nodes, "fp64", gamma, stream, None if w is None else np.zeros((n, n)), w)
+    name = "sf_hadamard_volume_surface" if with_volume else "sf_hadamard_surface"
+    check(getattr(lib(), name)(u.data_ptr(), uf.data_ptr(), E, n, d, FLUX[flux], y_vol.data_ptr(),
+                               y_face.data_ptr(), ctypes.byref(opts)), name)
+    del keep
+    return y_vol, y_face
 
 
 def basis_1d(n: int, nodes: str = "gl"):

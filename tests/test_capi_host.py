@@ -168,3 +168,30 @@ def test_tensor_apply_validation(sf):
     assert L.sf_basis_1d(4, 3, None, None) == -1
     assert L.sf_basis_1d(17, 0, None, None) == -2
     assert L.sf_basis_1d(4, 1, None, None) == 0
+
+
+@pytest.mark.parametrize("kind", ["gl", "gll"])
+@pytest.mark.parametrize("n", [2, 3, 4, 8, 13, 16])
+def test_surface_end_values_match_oracle(sf, orc, n, kind):
+    lm, lp = sf.surface_operator_1d(n, kind)
+    olm, olp = orc.lagrange_endpoints(n, kind)
+    assert np.abs(lm - olm).max() < 1e-13 * max(1.0, np.abs(olm).max())
+    assert np.abs(lp - olp).max() < 1e-13 * max(1.0, np.abs(olp).max())
+
+
+@pytest.mark.parametrize("fn", ["sf_hadamard_surface", "sf_hadamard_volume_surface"])
+def test_surface_validation(sf, fn):
+    L = sf.lib()
+    f = getattr(L, fn)
+    big = 10 ** 9
+    assert f(BAD, None, 4, 4, 3, 1, BAD + big, BAD + 2 * big, None) == -1          # null u_face
+    assert f(BAD, BAD + 3 * big, 4, 4, 3, 1, BAD + big, None, None) == -1          # null y_face
+    assert f(BAD, BAD + 3 * big, 4, 4, 3, 1, BAD + big, BAD + big, None) == -1     # y_face on y_vol
+    assert f(BAD, BAD + 3 * big, 4, 4, 3, 1, BAD + big, BAD + 3 * big, None) == -1  # y_face on u_face
+    assert f(BAD, BAD + 3 * big, 4, 4, 3, 1, BAD, BAD + 2 * big, None) == -1       # y_vol on u_vol
+    assert f(BAD, BAD + 3 * big, 4, 4, 2, 1, BAD + big, BAD + 2 * big, None) == -2  # Euler needs d = 3
+    o = sf.SfOpts(); L.sf_opts_init(ctypes.byref(o)); o.precision = 1
+    assert f(BAD, BAD + 3 * big, 4, 4, 3, 1, BAD + big, BAD + 2 * big, ctypes.byref(o)) == -2  # FP64 only
+    assert f(None, None, 0, 4, 3, 1, None, None, None) == 0                        # E = 0
+    assert L.sf_surface_operator_1d(0, 0, None, None) == -1
+    assert L.sf_surface_operator_1d(17, 0, None, None) == -2
