@@ -34,7 +34,8 @@
  *    thread-local detail string for the last failing call on that thread.
  *  - Non-physical Euler states (rho <= 0 or p <= 0) are outside the domain:
  *    the result is unspecified (NaN/Inf propagate) and nothing is checked on
- *    the device.  The FP64 kernels assume rho, p in [1e-60, 1e60].
+ *    the device.  The kernels assume rho and beta = rho/(2p) in about
+ *    [1e-30, 1e30] (products of up to four such means are formed).
  *  - Thread safety: the operator cache is mutex-protected; calls on distinct
  *    streams are independent.
  */
