@@ -65,6 +65,8 @@ def lib():
         L.oracle_basis_sparse.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ip, ip, dp]
         L.oracle_basis_1d.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
         L.oracle_tensor_apply.argtypes = [dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
+        L.oracle_curv_volume.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, dp, dp,
+                                         ctypes.c_double, dp]
         L.oracle_lagrange_endpoints.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
         L.oracle_surface.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      dp, dp, dp, ctypes.c_double, dp, dp]
@@ -199,6 +201,26 @@ def tensor_apply(u, n: int, d: int, M) -> np.ndarray:
         raise ValueError("shape mismatch")
     out = np.zeros_like(u)
     if lib().oracle_tensor_apply(_dp(u), u.shape[1], n, d, u.shape[0], _dp(M), _dp(out)) != 0:
+        raise ValueError("oracle rejected arguments")
+    return out
+
+
+def curv_volume(u, Ja, n: int, flux_kind: str = "euler", Q=None, w=None, nodes_kind="gl", gamma=1.4):
+    """Curvilinear volume term (3D) with the metric-averaged flux; Ja of shape
+    (3, 3, E, n^3) = [m][k][e][node], Ja^m_k = J d xi^m / d x_k."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    Ja = np.ascontiguousarray(Ja, dtype=np.float64)
+    nv = NVAR[flux_kind]
+    E = u.shape[1]
+    if u.shape != (nv, E, n ** 3) or Ja.shape != (3, 3, E, n ** 3):
+        raise ValueError("shape mismatch")
+    if Q is None or w is None:
+        _, w0, _, Q0 = operator_1d(n, nodes_kind)
+        Q = Q0 if Q is None else Q
+        w = w0 if w is None else w
+    Q = np.ascontiguousarray(Q, dtype=np.float64); w = np.ascontiguousarray(w, dtype=np.float64)
+    out = np.zeros_like(u)
+    if lib().oracle_curv_volume(_dp(u), _dp(Ja), E, n, FLUX[flux_kind], _dp(Q), _dp(w), gamma, _dp(out)) != 0:
         raise ValueError("oracle rejected arguments")
     return out
 

@@ -27,6 +27,9 @@
  *   - The Remark after Eq. (5): the same Hadamard product with alpha = 0 and
  *     facet cubature nodes, the surface terms.  oracle_lagrange_endpoints and
  *     oracle_surface give its plain definition (see there).
+ *   - Curvilinear elements (the Results section's warped grids): the
+ *     metric-averaged two-point flux in reference direction m,
+ *     sum_k f_k(u_i, u_j) (Ja^m_k(i) + Ja^m_k(j)) / 2; oracle_curv_volume.
  *   - Eq. (6) and the proof of Theorem 1: a polynomial basis chi evaluated
  *     on the nodes, its projection Pi with Pi chi = I, and the basis
  *     transformation applied direction by direction.  oracle_basis_1d and
@@ -526,6 +529,56 @@ int oracle_tensor_apply(const double *in, long E, int n, int d, int nvar, const 
         }
     }
     free(K);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Curvilinear volume term                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* The volume term on a curvilinear element: the dense definition of
+ * oracle_dense_volume with F_m[i][j] the metric-averaged two-point flux
+ *     F_m[i][j] = sum_k f_k(u_i, u_j) (Ja^m_k(i) + Ja^m_k(j)) / 2,
+ * f_k the Cartesian two-point flux in direction k and Ja^m_k = J d xi^m/d x_k
+ * the contravariant metric terms at the nodes.  Ja layout:
+ * Ja[(3 m + k) * E * N + e * N + node], 9 arrays (d = 3).  Output in the
+ * Cartesian conserved variables. */
+int oracle_curv_volume(const double *u, const double *Ja, long E, int n, int flux,
+                       const double *Q, const double *w, double gamma, double *out)
+{
+    const int d = 3;
+    if (!u || !Ja || !out || !Q || !w || E < 0 || n < 1) return -1;
+    int N = n * n * n;
+    int nv = flux_nvar(flux);
+    double *A = (double *)malloc(sizeof(double) * (size_t)d * N * N);
+    for (int m = 0; m < d; ++m) oracle_build_A(n, d, m, Q, w, A + (size_t)m * N * N);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long e = 0; e < E; ++e) {
+        double *ue = (double *)malloc(sizeof(double) * (size_t)N * nv);
+        double *ye = (double *)calloc((size_t)N * nv, sizeof(double));
+        double F[5], Fm[5];
+        for (int i = 0; i < N; ++i)
+            for (int v = 0; v < nv; ++v) ue[i * nv + v] = u[(size_t)v * E * N + (size_t)e * N + i];
+        for (int m = 0; m < d; ++m) {
+            const double *Am = A + (size_t)m * N * N;
+            for (int i = 0; i < N; ++i)
+                for (int j = 0; j < N; ++j) {
+                    for (int v = 0; v < nv; ++v) Fm[v] = 0.0;
+                    for (int k = 0; k < d; ++k) {
+                        const double a_i = Ja[(size_t)(3 * m + k) * E * N + (size_t)e * N + i];
+                        const double a_j = Ja[(size_t)(3 * m + k) * E * N + (size_t)e * N + j];
+                        oracle_flux(flux, ue + i * nv, ue + j * nv, k, gamma, F);
+                        for (int v = 0; v < nv; ++v) Fm[v] += F[v] * (a_i + a_j) / 2.0;
+                    }
+                    const double a = Am[(size_t)i * N + j];
+                    for (int v = 0; v < nv; ++v) ye[i * nv + v] += a * Fm[v];
+                }
+        }
+        for (int i = 0; i < N; ++i)
+            for (int v = 0; v < nv; ++v) out[(size_t)v * E * N + (size_t)e * N + i] = ye[i * nv + v];
+        free(ue); free(ye);
+    }
+    free(A);
     return 0;
 }
 

@@ -142,6 +142,59 @@ class MeshSpec:
     seed: int
 
 
+def reference_nodes(n: int, nodes: str = "gl") -> np.ndarray:
+    """The n nodes on [-1, 1] from numpy's Legendre routines (input
+    generation only: Gauss-Legendre roots, or +-1 and the roots of P'_{n-1})."""
+    if nodes == "gl":
+        return np.polynomial.legendre.leggauss(n)[0]
+    interior = np.polynomial.legendre.Legendre.basis(n - 1).deriv().roots()
+    return np.concatenate([[-1.0], np.sort(interior.real), [1.0]])
+
+
+def warped_mesh_metrics(E: int, n: int, nodes: str = "gl", amp: float = 0.02, length: float = 2 * math.pi):
+    """Contravariant metric terms Ja^m_k = J d xi^m / d x_k, shape (3, 3, E, n^3)
+    ([m][k][e][node], node = ix + n iy + n^2 iz), of a non-symmetrically
+    warped curvilinear mesh: the first E elements (x fastest) of a K^3 mesh of
+    the box [0, length]^3, K = ceil(E^(1/3)), mapped by
+        x = X + a sin(2 pi Y/L) sin(4 pi Z/L),  y = Y + a sin(4 pi X/L) sin(2 pi Z/L),
+        z = Z + a sin(2 pi X/L) sin(6 pi Y/L),  a = amp * L,
+    evaluated exactly (analytic Jacobian, cross-product form
+    Ja^1 = x_xi2 x x_xi3, Ja^2 = x_xi3 x x_xi1, Ja^3 = x_xi1 x x_xi2)."""
+    K = int(round(E ** (1.0 / 3.0)))
+    while K ** 3 < E:
+        K += 1
+    L = length
+    h = L / K
+    a = amp * L
+    xi = reference_nodes(n, nodes)
+    e = np.arange(E)
+    ex, ey, ez = e % K, (e // K) % K, e // (K * K)
+    node = np.arange(n ** 3)
+    ix, iy, iz = node % n, (node // n) % n, node // (n * n)
+    X = (ex[:, None] + (xi[ix][None, :] + 1) / 2) * h
+    Y = (ey[:, None] + (xi[iy][None, :] + 1) / 2) * h
+    Z = (ez[:, None] + (xi[iz][None, :] + 1) / 2) * h
+    w1, w2, w3 = 2 * math.pi / L, 4 * math.pi / L, 6 * math.pi / L
+    one = np.ones_like(X)
+    # M[i][j] = d x_i / d X_j
+    M = np.empty((3, 3) + X.shape)
+    M[0, 0] = one
+    M[0, 1] = a * w1 * np.cos(w1 * Y) * np.sin(w2 * Z)
+    M[0, 2] = a * w2 * np.sin(w1 * Y) * np.cos(w2 * Z)
+    M[1, 0] = a * w2 * np.cos(w2 * X) * np.sin(w1 * Z)
+    M[1, 1] = one
+    M[1, 2] = a * w1 * np.sin(w2 * X) * np.cos(w1 * Z)
+    M[2, 0] = a * w1 * np.cos(w1 * X) * np.sin(w3 * Y)
+    M[2, 1] = a * w3 * np.sin(w1 * X) * np.cos(w3 * Y)
+    M[2, 2] = one
+    cols = [M[:, j] * (h / 2) for j in range(3)]       # d x / d xi_j
+    Ja = np.empty((3, 3) + X.shape)
+    Ja[0] = np.cross(cols[1], cols[2], axis=0)
+    Ja[1] = np.cross(cols[2], cols[0], axis=0)
+    Ja[2] = np.cross(cols[0], cols[1], axis=0)
+    return np.ascontiguousarray(Ja)
+
+
 def serving_meshes(count: int = 64, base_seed: int = 5000, e_lo: int = 512, e_hi: int = 32768,
                    p_lo: int = 2, p_hi: int = 7) -> list:
     """Mesh k: p ~ U{p_lo..p_hi}, n = p + 1, E = round(exp(U[ln e_lo, ln e_hi])), seed base+k."""
