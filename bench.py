@@ -404,6 +404,29 @@ def main() -> int:
             f"(separate {1e3 * (kern_ms + ks):.1f} us)")
         del uf, yv_s, yf_s
 
+        # curvilinear elements: the same state on a warped mesh (analytic
+        # metric terms), metric-averaged flux
+        Ja = torch.from_numpy(W.warped_mesh_metrics(E, n)).cuda()
+        yc = torch.empty_like(ut)
+
+        def stepc():
+            sfhad.volume_curvilinear(ut, Ja, n, stream=stream, out=yc)
+
+        for _ in range(args.warmup):
+            stepc()
+        _, kc = timed_launches(torch, stepc, args.steps, stream)
+        cbytes = (2 * 5 + 9) * n ** 3 * 8 * E
+        result["curvilinear"] = {
+            "what": "sf_hadamard_volume_curvilinear, n = 8, 32768 warped elements (9 metric terms per node)",
+            "ms_per_launch": kc, "dof_per_s": dof / (kc * 1e-3), "elem_evals_per_s": E / (kc * 1e-3),
+            "hbm_algorithmic_GBps": round(cbytes / (kc * 1e-3) / 1e9, 1),
+            "hbm_frac": round(cbytes / (kc * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "vs_affine_kernel": kc / kern_ms,
+        }
+        log(f"[bench] curvilinear: {kc * 1e3:.1f} us/launch ({kc / kern_ms:.2f}x the affine kernel), "
+            f"{cbytes / (kc * 1e-3) / 1e9:.0f} GB/s algorithmic")
+        del Ja, yc
+
         # n = 4 workload: 100 launches captured in one HIP graph
         w2 = W.WORKLOADS["euler3d_n4_gl_e4096"]
         u2 = torch.from_numpy(w2.state()).cuda()

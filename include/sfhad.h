@@ -83,6 +83,7 @@ typedef enum {
 #define SF_MIN_N 2
 #define SF_MAX_N 16
 #define SF_MAX_N_EULER 13
+#define SF_MAX_N_CURV 10  /* curvilinear Euler term: the staged element must fit in LDS */
 
 /* Optional arguments of the _ex entry points.  Initialise with
  * sf_opts_init() and override fields as needed. */
@@ -122,6 +123,23 @@ int sf_hadamard_volume_ex(const double *u_nodes, int64_t elem_count, int n, int 
                           int flux_kind, double *out, const sf_opts *opts);
 int dense_hadamard_volume_ex(const double *u_nodes, int64_t elem_count, int n, int d,
                              int flux_kind, double *out, const sf_opts *opts);
+
+/* ---------------------------------------------------------------------
+ * Curvilinear elements (the Results section's warped grids).  The volume
+ * term of a curved element uses the metric-averaged two-point flux in
+ * reference direction m,
+ *     F_m[i][j] = sum_k f_k(u_i, u_j) (Ja^m_k(i) + Ja^m_k(j)) / 2,
+ * with f_k the Cartesian Chandrashekar flux in direction k and
+ * Ja^m_k = J d xi^m / d x_k the contravariant metric terms at the nodes;
+ * y = sum_m (A_m o F_m) 1 as before, in the Cartesian conserved variables.
+ *   Ja   device, 9 * E * n^3 doubles, Ja[(3 m + k) * E * n^3 + e * n^3 + node]
+ *        (m: reference direction, k: Cartesian component); not written
+ *   u, out  as sf_hadamard_volume (d = 3); out must not overlap u or Ja
+ * Euler flux only, FP64 only, 2 <= n <= SF_MAX_N_CURV (SF_ERR_UNSUPPORTED
+ * otherwise); opts as for the volume term.  With Ja^m_k = delta_mk it equals
+ * sf_hadamard_volume. */
+int sf_hadamard_volume_curvilinear(const double *u_nodes, const double *metric, int64_t elem_count, int n,
+                                   int flux_kind, double *out, const sf_opts *opts);
 
 /* ---------------------------------------------------------------------
  * Surface term (the Remark after Eq. (5): the same Hadamard product with

@@ -120,6 +120,23 @@ int run_surface(const double *u, const double *uf, int64_t E, int n, int d, int 
     return launch_sf_surface(r);
 }
 
+int run_curvilinear(const double *u, const double *Ja, int64_t E, int n, int flux, double *out,
+                    const sf_opts *opts) {
+    VolumeRequest r;
+    int st = validate(u, E, n, 3, flux, out, opts, false, r);
+    if (st != SF_OK) return st;
+    if (flux != SF_FLUX_EULER_CHANDRASHEKAR) return fail(SF_ERR_UNSUPPORTED, "the curvilinear term is built for the Euler flux");
+    if (r.precision != SF_PREC_FP64) return fail(SF_ERR_UNSUPPORTED, "the curvilinear term is built in FP64 only");
+    if (n > SF_MAX_N_CURV) return fail(SF_ERR_UNSUPPORTED, "the curvilinear term is built for n <= 10");
+    if (E == 0) return SF_OK;
+    if (!Ja) return fail(SF_ERR_ARG, "null metric terms");
+    const size_t vbytes = (size_t)(ipow(n, 3) * 5 * E) * sizeof(double);
+    const size_t mbytes = (size_t)(ipow(n, 3) * 9 * E) * sizeof(double);
+    if (overlaps(out, vbytes, Ja, mbytes)) return fail(SF_ERR_ARG, "out overlaps the metric terms");
+    r.aux = Ja;
+    return launch_sf_curvilinear(r);
+}
+
 int run(const double *u, int64_t E, int n, int d, int flux, double *out, const sf_opts *opts,
         bool dense) {
     VolumeRequest r;
@@ -172,6 +189,11 @@ int sf_hadamard_surface(const double *u, const double *uf, int64_t E, int n, int
 int sf_hadamard_volume_surface(const double *u, const double *uf, int64_t E, int n, int d, int flux, double *yv,
                                double *yf, const sf_opts *opts) {
     return run_surface(u, uf, E, n, d, flux, yv, yf, opts, kModeVolumeSurface);
+}
+
+int sf_hadamard_volume_curvilinear(const double *u, const double *Ja, int64_t E, int n, int flux, double *out,
+                                   const sf_opts *opts) {
+    return run_curvilinear(u, Ja, E, n, flux, out, opts);
 }
 
 int sf_surface_operator_1d(int n, int node_kind, double *lm, double *lp) {

@@ -178,6 +178,7 @@ struct ScalarFlux {
     using Real = double;
     static constexpr int NV = 1;
     static constexpr int NS = 1;
+    static constexpr int NX = 0;  // extra per-node input arrays (none)
     using Node = ScalarNode;
 
     static constexpr int NREF = 0;
@@ -248,6 +249,7 @@ struct EulerFP64 {
     using Real = double;
     static constexpr int NV = 5;
     static constexpr int NS = 7;
+    static constexpr int NX = 0;
     static constexpr int NREF = 4;  // rho_0, 1/rho_0, beta_0, 1/beta_0
     enum { S_R = 0, S_W = 1, S_B = 4, S_LR = 5, S_LB = 6 };
     using Node = EulerNode;
@@ -414,6 +416,7 @@ struct EulerFP32Split {
     using Real = float;
     static constexpr int NV = 5;
     static constexpr int NS = 10;
+    static constexpr int NX = 0;
     enum { S_R = 0, S_W = 1, S_B = 4, S_P = 5, S_LRH = 6, S_LRL = 7, S_LBH = 8, S_LBL = 9 };
     using Node = EulerNodeF;
     static constexpr float kSqrtTau = 1e-6f;
@@ -520,6 +523,114 @@ struct EulerFP32Split {
     }
 
     __device__ static int out_array(int k, int m) { return EulerFP64::out_array(k, m); }
+};
+
+
+// ---------------------------------------------------------------------------
+// Curvilinear Euler (FP64): the metric-averaged two-point flux in reference
+// direction m,
+//     F_m(u_i, u_j) = sum_k f_k(u_i, u_j) n_k,   n = (Ja^m(i) + Ja^m(j)) / 2,
+// with Ja^m_k = J d xi^m / d x_k the contravariant metric terms (the 9 extra
+// per-node inputs, stored halved).  Since the Chandrashekar flux is linear in
+// the direction, the sum is one flux with normal velocity {{v}} . n and
+// pressure term p_hat n:
+//     F^rho = rho^ln {{v}}.n,  F^(rho v_k) = F^rho {{v_k}} + p_hat n_k,
+//     F^E = F^rho [1/(2(gamma-1) beta^ln) + v_L.v_R/2] + p_hat {{v}}.n .
+// Velocities and results stay Cartesian (no rotation into a line frame).
+// ---------------------------------------------------------------------------
+struct EulerCurvNode {
+    double r, w0, w1, w2, b, lr, lb, n0, n1, n2;
+};
+
+struct EulerCurvFP64 {
+    using Real = double;
+    static constexpr int NV = 5;
+    static constexpr int NX = 9;   // Ja^m_k, m-major
+    static constexpr int NS = 16;  // EulerFP64's 7 (unrotated) + 9 halved metric terms
+    static constexpr int NREF = 4;
+    enum { S_R = 0, S_W = 1, S_B = 4, S_LR = 5, S_LB = 6, S_N = 7 };
+    using Node = EulerCurvNode;
+    using Consts = EulerFP64::Consts;
+
+    __device__ static void make_ref(const double *uc, double gamma, double *ref) {
+        EulerFP64::make_ref(uc, gamma, ref);
+    }
+    // uc: the 5 conserved variables, then the 9 metric terms
+    __device__ static void stage(const double *uc, const double *ref, double gamma, double *s) {
+        EulerFP64::stage(uc, ref, gamma, s);
+#pragma unroll
+        for (int j = 0; j < NX; ++j) s[S_N + j] = 0.5 * uc[NV + j];
+    }
+    __device__ static Node load(const double *lds, int arrstride, int idx, int m) {
+        Node A;
+        A.r = lds[S_R * arrstride + idx];
+        A.w0 = lds[(S_W + 0) * arrstride + idx];
+        A.w1 = lds[(S_W + 1) * arrstride + idx];
+        A.w2 = lds[(S_W + 2) * arrstride + idx];
+        A.b = lds[S_B * arrstride + idx];
+        A.lr = lds[S_LR * arrstride + idx];
+        A.lb = lds[S_LB * arrstride + idx];
+        A.n0 = lds[(S_N + 3 * m + 0) * arrstride + idx];
+        A.n1 = lds[(S_N + 3 * m + 1) * arrstride + idx];
+        A.n2 = lds[(S_N + 3 * m + 2) * arrstride + idx];
+        return A;
+    }
+    __device__ static Node load_partner(const double *lds, int arrstride, int idx, int m) {
+        return load(lds, arrstride, idx, m);
+    }
+    __device__ static Consts consts(double cg) { return EulerFP64::consts(cg); }
+
+    __device__ static void pair(const Node &A, const Node &C, const Consts &K, double *F) {
+        const double dr = A.r - C.r, sr = A.r + C.r;
+        const double db = A.b - C.b, sb = A.b + C.b;
+        double Nr = dr, Dr = A.lr - C.lr;
+        double Nb = db, Db = A.lb - C.lb;
+        if (__builtin_fabs(Dr) < K.thr_r) {  // near-equal densities: series
+            const double dr2 = dr * dr, sr2 = sr * sr;
+            const double u = dr2 * __builtin_amdgcn_rcp(sr2);
+            Nr = pin(0.5 * sr * sr2);
+            Dr = __builtin_fma(dr2, __builtin_fma(u, K.c5, K.c3), sr2);
+        }
+        if (__builtin_fabs(Db) < K.thr_b) {  // near-equal beta: series, times cg
+            const double db2 = db * db, sb2 = sb * sb;
+            const double u = db2 * __builtin_amdgcn_rcp(sb2);
+            Nb = pin(0.5 * sb * sb2);
+            Db = K.cg * __builtin_fma(db2, __builtin_fma(u, K.c5, K.c3), sb2);
+        }
+        const double DrNb = Dr * Nb;
+        const double R = rcp_fine(DrNb * sb);
+        const double rho_ln = Nr * (Nb * sb) * R;
+        const double cg_ibeta_ln = Db * (Dr * sb) * R;
+        const double phat = (0.5 * sr) * DrNb * R;
+
+        const double v0 = A.w0 + C.w0, v1 = A.w1 + C.w1, v2 = A.w2 + C.w2;     // {{v}}
+        const double n0 = A.n0 + C.n0, n1 = A.n1 + C.n1, n2 = A.n2 + C.n2;     // averaged Ja^m
+        const double vn = __builtin_fma(v0, n0, __builtin_fma(v1, n1, v2 * n2));
+        const double ww = __builtin_fma(A.w0, C.w0, __builtin_fma(A.w1, C.w1, A.w2 * C.w2));
+        const double F0 = rho_ln * vn;
+        F[0] = F0;
+        F[1] = __builtin_fma(F0, v0, phat * n0);
+        F[2] = __builtin_fma(F0, v1, phat * n1);
+        F[3] = __builtin_fma(F0, v2, phat * n2);
+        F[4] = __builtin_fma(F0, __builtin_fma(2.0, ww, cg_ibeta_ln), phat * vn);
+    }
+
+    // physical flux f(u) . Ja^m at the node
+    __device__ static void diag(const Node &A, double gamma, double *F) {
+        const double p = 0.5 * A.r * rcp_fine(A.b);
+        const double v0 = A.w0 + A.w0, v1 = A.w1 + A.w1, v2 = A.w2 + A.w2;
+        const double n0 = A.n0 + A.n0, n1 = A.n1 + A.n1, n2 = A.n2 + A.n2;
+        const double vn = __builtin_fma(v0, n0, __builtin_fma(v1, n1, v2 * n2));
+        const double rvn = A.r * vn;
+        const double q = __builtin_fma(v0, v0, __builtin_fma(v1, v1, v2 * v2));
+        F[0] = rvn;
+        F[1] = __builtin_fma(rvn, v0, p * n0);
+        F[2] = __builtin_fma(rvn, v1, p * n1);
+        F[3] = __builtin_fma(rvn, v2, p * n2);
+        F[4] = vn * __builtin_fma(gamma / (gamma - 1.0), p, 0.5 * A.r * q);
+    }
+
+    __device__ static int out_array(int k, int) { return k; }
 };
 
 }  // namespace dev

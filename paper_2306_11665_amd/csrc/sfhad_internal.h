@@ -48,6 +48,8 @@ struct VolumeRequest {
     const double *uf = nullptr;
     double *yf = nullptr;
     int mode = 0;
+    // curvilinear volume term: the 9 metric-term arrays, [m][k][e][node]
+    const double *aux = nullptr;
 };
 enum { kModeVolume = 0, kModeSurface = 1, kModeVolumeSurface = 2 };
 
@@ -56,6 +58,7 @@ enum { kModeVolume = 0, kModeSurface = 1, kModeVolumeSurface = 2 };
 // SF_ERR_HIP when the launch fails.
 int launch_sf_volume(const VolumeRequest &r);
 int launch_sf_surface(const VolumeRequest &r);  // kModeSurface or kModeVolumeSurface
+int launch_sf_curvilinear(const VolumeRequest &r);
 int launch_dense_volume(const VolumeRequest &r);
 
 // ---------------------------------------------------------------------------

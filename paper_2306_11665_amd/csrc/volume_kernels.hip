@@ -141,7 +141,7 @@ struct VolumeWork {
 template <int N, int DIM, class P, class Op, class Work = VolumeWork>
 __device__ __forceinline__ void sf_block(const double *__restrict__ u, double *__restrict__ out, int64_t E,
                                          int64_t e0, const Op &op, double gamma, double *lds, double *sref,
-                                         const Work &work = Work{}) {
+                                         const Work &work = Work{}, const double *__restrict__ aux = nullptr) {
     using G = Geom<N, DIM>;
     using L = SfLayout<N, DIM, P>;
     using R = typename P::Real;
@@ -169,13 +169,15 @@ __device__ __forceinline__ void sf_block(const double *__restrict__ u, double *_
     }
     // every load of the staging pass is issued before any conversion
     constexpr int SPT = (G::EPB * G::NODES + G::THREADS - 1) / G::THREADS;  // nodes per thread
-    double uc[SPT][P::NV];
+    double uc[SPT][P::NV + P::NX];  // conserved variables, then P::NX extra inputs from aux
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
         const int i = tid + k * G::THREADS;
         if (i < nvalid) {
 #pragma unroll
             for (int v = 0; v < P::NV; ++v) uc[k][v] = u[v * vstride + gbase + i];
+#pragma unroll
+            for (int x = 0; x < P::NX; ++x) uc[k][P::NV + x] = aux[x * vstride + gbase + i];
         }
     }
 #pragma unroll
@@ -442,6 +444,55 @@ int dispatch_surface_n(const VolumeRequest &r) {
     return SF_ERR_UNSUPPORTED;
 }
 
+// ---------------------------------------------------------------------------
+// Curvilinear elements: the volume kernel with the metric-averaged flux
+// (EulerCurvFP64); the 9 metric terms per node are staged with the state.
+template <int N>
+struct CurvArgs {
+    const double *u;
+    const double *Ja;
+    double *out;
+    int64_t E;
+    double gamma;
+    OpArg<N> op;
+};
+
+template <int N>
+__global__ void __launch_bounds__((Geom<N, 3>::THREADS))
+sf_curv_kernel(const CurvArgs<N>) {
+    using L = SfLayout<N, 3, EulerCurvFP64>;
+    __shared__ double lds[L::LDS_D];
+    __shared__ double sref[L::REF_D];
+    const auto A = kernel_args<CurvArgs<N>>();
+    sf_block<N, 3, EulerCurvFP64>(A->u, A->out, A->E, (int64_t)blockIdx.x * Geom<N, 3>::EPB, KernargOp<N>{&A->op},
+                                  A->gamma, lds, sref, VolumeWork{}, A->Ja);
+}
+
+template <int N>
+int launch_curv(const VolumeRequest &r) {
+    using G = Geom<N, 3>;
+    const int64_t blocks = (r.E + G::EPB - 1) / G::EPB;
+    if (blocks > 0x7fffffffLL) {
+        set_error("element count too large for one launch");
+        return SF_ERR_UNSUPPORTED;
+    }
+    CurvArgs<N> a;
+    a.u = r.u;
+    a.Ja = r.aux;
+    a.out = r.out;
+    a.E = r.E;
+    a.gamma = r.gamma;
+    for (int i = 0; i < N * N; ++i) a.op.Q[i] = r.op.Q[i];
+    for (int i = 0; i < N; ++i) a.op.w[i] = r.op.w[i];
+    hipLaunchKernelGGL((sf_curv_kernel<N>), dim3((unsigned)blocks), dim3(G::THREADS), 0, r.stream, a);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) {
+        set_error(std::string("sf_curv_kernel launch: ") + hipGetErrorString(err));
+        return SF_ERR_HIP;
+    }
+    return SF_OK;
+}
+
 // Dispatch on n for a fixed (DIM, policy); n range [2, NMAX].
 template <int DIM, class P, int NMAX>
 int dispatch_n(const VolumeRequest &r) {
@@ -595,6 +646,24 @@ int launch_sf_surface(const VolumeRequest &r) {
         default: break;
     }
     set_error("flux / dimension combination not built");
+    return SF_ERR_UNSUPPORTED;
+}
+
+int launch_sf_curvilinear(const VolumeRequest &r) {
+    using namespace dev;
+    switch (r.n) {
+        case 2: return launch_curv<2>(r);
+        case 3: return launch_curv<3>(r);
+        case 4: return launch_curv<4>(r);
+        case 5: return launch_curv<5>(r);
+        case 6: return launch_curv<6>(r);
+        case 7: return launch_curv<7>(r);
+        case 8: return launch_curv<8>(r);
+        case 9: return launch_curv<9>(r);
+        case 10: return launch_curv<10>(r);
+        default: break;
+    }
+    set_error("the curvilinear kernel is built for 2 <= n <= 10");
     return SF_ERR_UNSUPPORTED;
 }
 

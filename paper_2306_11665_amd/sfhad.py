@@ -85,6 +85,8 @@ def lib() -> ctypes.CDLL:
         for name in ("sf_hadamard_surface", "sf_hadamard_volume_surface"):
             getattr(L, name).argtypes = [vp, vp, i64, ci, ci, ci, vp, vp, ctypes.POINTER(SfOpts)]
             getattr(L, name).restype = ci
+        L.sf_hadamard_volume_curvilinear.argtypes = [vp, vp, i64, ci, ci, vp, ctypes.POINTER(SfOpts)]
+        L.sf_hadamard_volume_curvilinear.restype = ci
         L.sf_surface_operator_1d.argtypes = [ci, ci, _dp, _dp]
         L.sf_surface_operator_1d.restype = ci
         L.sf_basis_1d.argtypes = [ci, ci, _dp, _dp]
@@ -173,6 +175,23 @@ def volume(u, n: int, d: int, flux: str, **kw):
 def dense_volume(u, n: int, d: int, flux: str, **kw):
     """Same term over all n^(2d) pairs (dense_hadamard_volume_ex)."""
     return _call("dense_hadamard_volume_ex", u, n, d, flux, **kw)
+
+
+def volume_curvilinear(u, Ja, n: int, flux: str = "euler", *, nodes="gl", gamma=1.4, stream=None, out=None):
+    """Curvilinear volume term (sf_hadamard_volume_curvilinear): u (5, E, n^3),
+    Ja (3, 3, E, n^3) = [m][k][e][node] contravariant metric terms."""
+    import torch
+    _check_tensor(u, flux, n, 3)
+    E = u.shape[1]
+    if (not isinstance(Ja, torch.Tensor) or Ja.device.type != "cuda" or Ja.dtype != torch.float64
+            or not Ja.is_contiguous() or tuple(Ja.shape) != (3, 3, E, n ** 3)):
+        raise ValueError(f"Ja must be a contiguous float64 CUDA tensor (3, 3, {E}, {n ** 3})")
+    out = torch.empty_like(u) if out is None else out
+    opts, keep = make_opts(nodes, "fp64", gamma, stream)
+    check(lib().sf_hadamard_volume_curvilinear(u.data_ptr(), Ja.data_ptr(), E, n, FLUX[flux], out.data_ptr(),
+                                               ctypes.byref(opts)), "sf_hadamard_volume_curvilinear")
+    del keep
+    return out
 
 
 def surface_operator_1d(n: int, nodes: str = "gl"):

@@ -195,3 +195,17 @@ def test_surface_validation(sf, fn):
     assert f(None, None, 0, 4, 3, 1, None, None, None) == 0                        # E = 0
     assert L.sf_surface_operator_1d(0, 0, None, None) == -1
     assert L.sf_surface_operator_1d(17, 0, None, None) == -2
+
+
+def test_curvilinear_validation(sf):
+    L = sf.lib()
+    f = L.sf_hadamard_volume_curvilinear
+    big = 10 ** 9
+    assert f(BAD, None, 4, 4, 1, BAD + big, None) == -1               # null metric terms
+    assert f(BAD, BAD + 2 * big, 4, 4, 0, BAD + big, None) == -2      # Euler only
+    assert f(BAD, BAD + 2 * big, 4, 11, 1, BAD + big, None) == -2     # n <= 10
+    assert f(BAD, BAD + 2 * big, 4, 4, 1, BAD + 2 * big, None) == -1  # out on the metric terms
+    assert f(BAD, BAD + 2 * big, 4, 4, 1, BAD, None) == -1            # out on u
+    o = sf.SfOpts(); L.sf_opts_init(ctypes.byref(o)); o.precision = 1
+    assert f(BAD, BAD + 2 * big, 4, 4, 1, BAD + big, ctypes.byref(o)) == -2
+    assert f(None, None, 0, 4, 1, None, None) == 0                    # E = 0
