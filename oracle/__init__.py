@@ -65,6 +65,11 @@ def lib():
         L.oracle_basis_sparse.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ip, ip, dp]
         L.oracle_basis_1d.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
         L.oracle_tensor_apply.argtypes = [dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
+        L.oracle_entropy_vars.argtypes = [dp, ctypes.c_double, dp]
+        L.oracle_entropy_vars.restype = None
+        L.oracle_conserved_from_entropy.argtypes = [dp, ctypes.c_double, dp]
+        L.oracle_conserved_from_entropy.restype = None
+        L.oracle_entropy_trace.argtypes = [dp, ctypes.c_long, ctypes.c_int, dp, dp, ctypes.c_double, dp]
         L.oracle_curv_volume.argtypes = [dp, dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, dp, dp,
                                          ctypes.c_double, dp]
         L.oracle_lagrange_endpoints.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
@@ -203,6 +208,33 @@ def tensor_apply(u, n: int, d: int, M) -> np.ndarray:
     if lib().oracle_tensor_apply(_dp(u), u.shape[1], n, d, u.shape[0], _dp(M), _dp(out)) != 0:
         raise ValueError("oracle rejected arguments")
     return out
+
+
+def entropy_vars(u, gamma: float = 1.4) -> np.ndarray:
+    u = np.ascontiguousarray(u, dtype=np.float64); v = np.zeros(5)
+    lib().oracle_entropy_vars(_dp(u), gamma, _dp(v))
+    return v
+
+
+def conserved_from_entropy(v, gamma: float = 1.4) -> np.ndarray:
+    v = np.ascontiguousarray(v, dtype=np.float64); u = np.zeros(5)
+    lib().oracle_conserved_from_entropy(_dp(v), gamma, _dp(u))
+    return u
+
+
+def entropy_trace(u, n: int, nodes_kind: str = "gl", gamma: float = 1.4, lm=None, lp=None) -> np.ndarray:
+    """Entropy-projected facet states u(E_f v(u)), shape (5, E, 6, n^2)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    E = u.shape[1]
+    if u.shape != (5, E, n ** 3):
+        raise ValueError("shape mismatch")
+    if lm is None or lp is None:
+        lm, lp = lagrange_endpoints(n, nodes_kind)
+    lm = np.ascontiguousarray(lm, dtype=np.float64); lp = np.ascontiguousarray(lp, dtype=np.float64)
+    uf = np.zeros((5, E, 6, n * n))
+    if lib().oracle_entropy_trace(_dp(u), E, n, _dp(lm), _dp(lp), gamma, _dp(uf)) != 0:
+        raise ValueError("oracle rejected arguments")
+    return uf
 
 
 def curv_volume(u, Ja, n: int, flux_kind: str = "euler", Q=None, w=None, nodes_kind="gl", gamma=1.4):

@@ -30,6 +30,11 @@
  *   - Curvilinear elements (the Results section's warped grids): the
  *     metric-averaged two-point flux in reference direction m,
  *     sum_k f_k(u_i, u_j) (Ja^m_k(i) + Ja^m_k(j)) / 2; oracle_curv_volume.
+ *   - Entropy projection (the Results section's uncollocated scheme uses
+ *     it with the sum-factorized Hadamard products): facet states as the
+ *     conserved variables of the facet-interpolated entropy variables,
+ *     u(E_f v(u)); oracle_entropy_vars / oracle_conserved_from_entropy /
+ *     oracle_entropy_trace.
  *   - Eq. (6) and the proof of Theorem 1: a polynomial basis chi evaluated
  *     on the nodes, its projection Pi with Pi chi = I, and the basis
  *     transformation applied direction by direction.  oracle_basis_1d and
@@ -529,6 +534,109 @@ int oracle_tensor_apply(const double *in, long E, int n, int d, int nvar, const 
         }
     }
     free(K);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Entropy variables and the entropy-projected facet states                  */
+/* ------------------------------------------------------------------------ */
+
+/* Entropy variables v = dU/du of U = -rho s/(gamma - 1), s = ln p - gamma ln rho:
+ *   v = ((gamma - s)/(gamma - 1) - rho |vel|^2/(2p), rho vel/p, -rho/p). */
+void oracle_entropy_vars(const double *u, double gamma, double *v)
+{
+    const double rho = u[0];
+    const double vx = u[1] / rho, vy = u[2] / rho, vz = u[3] / rho;
+    const double q = vx * vx + vy * vy + vz * vz;
+    const double p = (gamma - 1.0) * (u[4] - 0.5 * rho * q);
+    const double s = log(p) - gamma * log(rho);
+    v[0] = (gamma - s) / (gamma - 1.0) - rho * q / (2.0 * p);
+    v[1] = rho * vx / p;
+    v[2] = rho * vy / p;
+    v[3] = rho * vz / p;
+    v[4] = -rho / p;
+}
+
+/* The inverse map: rho/p = -v4, vel = v1..3 / (-v4),
+ * s = gamma - (gamma - 1)(v0 + (rho/p)|vel|^2/2), and from
+ * s = ln p - gamma ln rho = (1 - gamma) ln rho - ln(-v4):
+ * rho = exp((s + ln(-v4)) / (1 - gamma)), p = rho/(-v4). */
+void oracle_conserved_from_entropy(const double *v, double gamma, double *u)
+{
+    const double rp = -v[4];
+    const double vx = v[1] / rp, vy = v[2] / rp, vz = v[3] / rp;
+    const double q = vx * vx + vy * vy + vz * vz;
+    const double s = gamma - (gamma - 1.0) * (v[0] + rp * q / 2.0);
+    const double rho = exp((s + log(rp)) / (1.0 - gamma));
+    const double p = rho / rp;
+    u[0] = rho;
+    u[1] = rho * vx;
+    u[2] = rho * vy;
+    u[3] = rho * vz;
+    u[4] = p / (gamma - 1.0) + 0.5 * rho * q;
+}
+
+/* Entropy-projected facet states (3D Euler): for face f = 2m + s, facet node
+ * t (layout of oracle_surface),
+ *     u_face[t] = u( (E_f v)[t] ),   E_f = l_s^T in position m, I elsewhere,
+ * the interpolation of the nodal entropy variables to the facet, built as an
+ * explicit Kronecker product and applied as a dense matrix-vector product.
+ * (With as many nodes as modes per direction the L2 projection of v onto the
+ * polynomials is v itself, so this is u(V_f P v(u)).) */
+int oracle_entropy_trace(const double *u, long E, int n, const double *lm, const double *lp, double gamma,
+                         double *uf)
+{
+    const int d = 3;
+    if (!u || !uf || !lm || !lp || E < 0 || n < 1) return -1;
+    const int N = n * n * n, T = n * n, NF = 6;
+    double *I = (double *)calloc((size_t)n * n, sizeof(double));
+    for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+    double *Ef = (double *)malloc(sizeof(double) * (size_t)NF * T * N);
+    double *cur = (double *)malloc(sizeof(double) * (size_t)T * N);
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)T * N);
+    for (int f = 0; f < NF; ++f) {
+        const int m = f / 2;
+        const double *ls = (f % 2) ? lp : lm;
+        int rows = (d - 1 == m) ? 1 : n, cols = n;
+        if (d - 1 == m) memcpy(cur, ls, sizeof(double) * n);
+        else memcpy(cur, I, sizeof(double) * n * n);
+        for (int k = d - 2; k >= 0; --k) {
+            if (k == m) {
+                kron(cur, rows, cols, ls, 1, n, tmp);
+                cols *= n;
+            } else {
+                kron(cur, rows, cols, I, n, n, tmp);
+                rows *= n;
+                cols *= n;
+            }
+            memcpy(cur, tmp, sizeof(double) * (size_t)rows * cols);
+        }
+        memcpy(Ef + (size_t)f * T * N, cur, sizeof(double) * (size_t)T * N);
+    }
+    free(cur); free(tmp); free(I);
+#pragma omp parallel for schedule(static)
+    for (long e = 0; e < E; ++e) {
+        double *ve = (double *)malloc(sizeof(double) * (size_t)N * 5);
+        double ue[5], vf[5], uo[5];
+        for (int i = 0; i < N; ++i) {
+            for (int k = 0; k < 5; ++k) ue[k] = u[(size_t)k * E * N + (size_t)e * N + i];
+            oracle_entropy_vars(ue, gamma, ve + i * 5);
+        }
+        for (int f = 0; f < NF; ++f) {
+            const double *Ff = Ef + (size_t)f * T * N;
+            for (int t = 0; t < T; ++t) {
+                for (int k = 0; k < 5; ++k) vf[k] = 0.0;
+                for (int j = 0; j < N; ++j) {
+                    const double c = Ff[(size_t)t * N + j];
+                    for (int k = 0; k < 5; ++k) vf[k] += c * ve[j * 5 + k];
+                }
+                oracle_conserved_from_entropy(vf, gamma, uo);
+                for (int k = 0; k < 5; ++k) uf[(size_t)k * E * NF * T + ((size_t)e * NF + f) * T + t] = uo[k];
+            }
+        }
+        free(ve);
+    }
+    free(Ef);
     return 0;
 }
 
