@@ -427,6 +427,24 @@ def main() -> int:
             f"{cbytes / (kc * 1e-3) / 1e9:.0f} GB/s algorithmic")
         del Ja, yc
 
+        # entropy-projected facet states (GLL: facet values stay physical for
+        # the random per-node state)
+        ufe = torch.empty((5, E, 6, n * n), dtype=torch.float64, device="cuda")
+
+        def stepe():
+            sfhad.entropy_trace(ut, n, nodes="gll", stream=stream, out=ufe)
+
+        for _ in range(args.warmup):
+            stepe()
+        _, ke = timed_launches(torch, stepe, args.steps, stream)
+        ebytes = 5 * 8 * (n ** 3 + 6 * n * n) * E
+        result["entropy_trace"] = {
+            "what": "sf_entropy_trace, n = 8 (GLL), 32768 elements", "ms_per_launch": ke,
+            "hbm_algorithmic_GBps": round(ebytes / (ke * 1e-3) / 1e9, 1),
+            "hbm_frac": round(ebytes / (ke * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+        log(f"[bench] entropy trace: {ke * 1e3:.1f} us/launch, {ebytes / (ke * 1e-3) / 1e9:.0f} GB/s")
+        del ufe
+
         # n = 4 workload: 100 launches captured in one HIP graph
         w2 = W.WORKLOADS["euler3d_n4_gl_e4096"]
         u2 = torch.from_numpy(w2.state()).cuda()

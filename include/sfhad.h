@@ -173,6 +173,21 @@ int sf_hadamard_surface(const double *u_vol, const double *u_face, int64_t elem_
 int sf_hadamard_volume_surface(const double *u_vol, const double *u_face, int64_t elem_count, int n, int d,
                                int flux_kind, double *y_vol, double *y_face, const sf_opts *opts);
 
+/* Entropy-projected facet states of 3D Euler nodal states, the facet input
+ * of the surface term in an entropy-stable scheme:
+ *     u_face[t] = u( sum_k l_s[k] v(u_k) )
+ * over the n nodes of the line through facet node t of face (m, s), with
+ * v = dU/du the entropy variables of U = -rho s/(gamma - 1) and u(.) the
+ * inverse map (with as many nodes as modes per direction the L2 projection
+ * of v is v itself, so this is u(V_f P v(u))).
+ *   u_nodes  device, 5 * E * n^3 doubles, the volume layout
+ *   u_face   device, 5 * E * 6 * n^2 doubles, [v][e][f][t] as for
+ *            sf_hadamard_surface; fully overwritten; must not overlap u_nodes
+ * 2 <= n <= 13, FP64; opts: node_kind, gamma, stream (NULL = defaults).
+ * States must be physical (rho, p > 0) and so must the interpolated entropy
+ * variables (v_4 < 0); nothing is checked on the device. */
+int sf_entropy_trace(const double *u_nodes, int64_t elem_count, int n, double *u_face, const sf_opts *opts);
+
 /* The Lagrange basis of the n nodes at the interval ends (host, FP64):
  * lm[k] = l_k(-1), lp[k] = l_k(+1); either may be NULL.  No GPU needed. */
 int sf_surface_operator_1d(int n, int node_kind, double *lm_host, double *lp_host);

@@ -196,6 +196,28 @@ int sf_hadamard_volume_curvilinear(const double *u, const double *Ja, int64_t E,
     return run_curvilinear(u, Ja, E, n, flux, out, opts);
 }
 
+int sf_entropy_trace(const double *u, int64_t E, int n, double *uf, const sf_opts *opts) {
+    sf_opts o;
+    sf_opts_init(&o);
+    if (opts) o = *opts;
+    if (E < 0) return fail(SF_ERR_ARG, "elem_count must be >= 0");
+    if (n < 1) return fail(SF_ERR_ARG, "n must be >= 1");
+    if (o.node_kind != SF_NODES_GAUSS_LEGENDRE && o.node_kind != SF_NODES_GAUSS_LOBATTO)
+        return fail(SF_ERR_ARG, "unknown node_kind");
+    if (!(o.gamma > 1.0) || !std::isfinite(o.gamma)) return fail(SF_ERR_ARG, "gamma must be finite and > 1");
+    if (o.precision != SF_PREC_FP64) return fail(SF_ERR_UNSUPPORTED, "the entropy trace is built in FP64 only");
+    if (n < SF_MIN_N || n > SF_MAX_N_EULER) return fail(SF_ERR_UNSUPPORTED, "the entropy trace is built for 2 <= n <= 13");
+    if (E == 0) return SF_OK;
+    if (!u || !uf) return fail(SF_ERR_ARG, "null u_nodes or u_face");
+    if (E > INT64_MAX / (ipow(n, 3) * 5 * (int64_t)sizeof(double))) return fail(SF_ERR_ARG, "elem_count too large");
+    const size_t vbytes = (size_t)(ipow(n, 3) * 5 * E) * sizeof(double);
+    const size_t fbytes = (size_t)(6 * ipow(n, 2) * 5 * E) * sizeof(double);
+    if (overlaps(u, vbytes, uf, fbytes)) return fail(SF_ERR_ARG, "u_face overlaps u_nodes");
+    Operator1D op;
+    if (!get_operator(n, o.node_kind, op)) return fail(SF_ERR_UNSUPPORTED, "operator construction failed");
+    return launch_entropy_trace(u, uf, E, n, o.gamma, op, reinterpret_cast<hipStream_t>(o.stream));
+}
+
 int sf_surface_operator_1d(int n, int node_kind, double *lm, double *lp) {
     if (n < 1) return fail(SF_ERR_ARG, "n must be >= 1");
     if (node_kind != SF_NODES_GAUSS_LEGENDRE && node_kind != SF_NODES_GAUSS_LOBATTO)

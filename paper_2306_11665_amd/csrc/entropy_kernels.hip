@@ -1,0 +1,144 @@
+// Entropy-projected facet states for the surface term (3D Euler, FP64):
+//     u_face[t] = u( sum_k l_s[k] v(u_k) )
+// over the n nodes u_k of the line through facet node t of face (m, s): the
+// conserved variables of the facet-interpolated entropy variables (with as
+// many nodes as modes per direction the L2 projection of v is v itself, so
+// this is u(V_f P v(u))).  v = dU/du for U = -rho s/(gamma - 1),
+// s = ln p - gamma ln rho:
+//     v = ((gamma - s)/(gamma - 1) - rho |vel|^2/(2p), rho vel/p, -rho/p),
+// and its inverse from rho/p = -v_4: vel = v_1..3/(rho/p),
+// s = gamma - (gamma - 1)(v_0 + (rho/p)|vel|^2/2),
+// rho = exp((s + ln(rho/p))/(1 - gamma)), p = rho/(rho/p).
+//
+// One workgroup per element: the nodal entropy variables go to LDS (one
+// padded array per component), then each thread takes facet nodes in the
+// output order (face-major, t fastest: coalesced stores) and interpolates
+// along its line.  HBM-bound: 8 B x 5 x (n^3 + 6 n^2) per element.
+#include "kernels_common.h"
+#include "sfhad_internal.h"
+
+namespace sfhad {
+namespace dev {
+
+constexpr int kTraceThreads = 256;
+
+template <int N>
+struct TraceArgs {
+    const double *u;
+    double *uf;
+    int64_t E;
+    double gamma;
+    double lm[N];
+    double lp[N];
+};
+
+template <int N>
+__device__ __forceinline__ int trace_node(int t, int k, int m) {
+    if (m == 0) return k + N * t;                          // t = iy + n iz
+    if (m == 1) return (t % N) + N * k + N * N * (t / N);  // t = ix + n iz
+    return t + N * N * k;                                  // t = ix + n iy
+}
+
+template <int N>
+__global__ void __launch_bounds__(kTraceThreads) entropy_trace_kernel(const TraceArgs<N>) {
+    constexpr int NODES = N * N * N, T = N * N, NF = 6, PAD = NODES + NODES / N;
+    __shared__ double sv[5 * PAD];
+    const auto A = kernel_args<TraceArgs<N>>();
+    const int tid = threadIdx.x;
+    const int64_t e = blockIdx.x;
+    const double g = A->gamma;
+    const size_t vs = (size_t)A->E * NODES, base = (size_t)e * NODES;
+    for (int i = tid; i < NODES; i += kTraceThreads) {
+        const double rho = A->u[base + i];
+        const double irho = 1.0 / rho;
+        const double vx = A->u[vs + base + i] * irho, vy = A->u[2 * vs + base + i] * irho,
+                     vz = A->u[3 * vs + base + i] * irho;
+        const double q = vx * vx + vy * vy + vz * vz;
+        const double p = (g - 1.0) * (A->u[4 * vs + base + i] - 0.5 * rho * q);
+        const double rp = rho / p;
+        const double s = log(p) - g * log(rho);
+        const int li = i + i / N;
+        sv[li] = (g - s) / (g - 1.0) - 0.5 * rp * q;
+        sv[PAD + li] = rp * vx;
+        sv[2 * PAD + li] = rp * vy;
+        sv[3 * PAD + li] = rp * vz;
+        sv[4 * PAD + li] = -rp;
+    }
+    __syncthreads();
+    const size_t fs = (size_t)A->E * NF * T;
+    const size_t fbase = (size_t)e * NF * T;
+    for (int j = tid; j < NF * T; j += kTraceThreads) {
+        const int f = j / T, t = j - f * T;
+        const int m = f >> 1;
+        double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double l = (f & 1) ? A->lp[k] : A->lm[k];
+            const int nd = trace_node<N>(t, k, m);
+            const int li = nd + nd / N;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) v[c] = __builtin_fma(l, sv[c * PAD + li], v[c]);
+        }
+        const double rp = -v[4];
+        const double vx = v[1] / rp, vy = v[2] / rp, vz = v[3] / rp;
+        const double q = vx * vx + vy * vy + vz * vz;
+        const double s = g - (g - 1.0) * (v[0] + 0.5 * rp * q);
+        const double rho = exp((s + log(rp)) / (1.0 - g));
+        const double p = rho / rp;
+        A->uf[fbase + j] = rho;
+        A->uf[fs + fbase + j] = rho * vx;
+        A->uf[2 * fs + fbase + j] = rho * vy;
+        A->uf[3 * fs + fbase + j] = rho * vz;
+        A->uf[4 * fs + fbase + j] = p / (g - 1.0) + 0.5 * rho * q;
+    }
+}
+
+template <int N>
+int launch_trace(const double *u, double *uf, int64_t E, double gamma, const Operator1D &op, hipStream_t st) {
+    if (E > 0x7fffffffLL) {
+        set_error("element count too large for one launch");
+        return SF_ERR_UNSUPPORTED;
+    }
+    TraceArgs<N> a;
+    a.u = u;
+    a.uf = uf;
+    a.E = E;
+    a.gamma = gamma;
+    for (int i = 0; i < N; ++i) {
+        a.lm[i] = op.lm[i];
+        a.lp[i] = op.lp[i];
+    }
+    hipLaunchKernelGGL((entropy_trace_kernel<N>), dim3((unsigned)E), dim3(kTraceThreads), 0, st, a);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) {
+        set_error(std::string("entropy_trace_kernel launch: ") + hipGetErrorString(err));
+        return SF_ERR_HIP;
+    }
+    return SF_OK;
+}
+
+}  // namespace dev
+
+int launch_entropy_trace(const double *u, double *uf, int64_t E, int n, double gamma, const Operator1D &op,
+                         hipStream_t st) {
+    using namespace dev;
+    switch (n) {
+        case 2: return launch_trace<2>(u, uf, E, gamma, op, st);
+        case 3: return launch_trace<3>(u, uf, E, gamma, op, st);
+        case 4: return launch_trace<4>(u, uf, E, gamma, op, st);
+        case 5: return launch_trace<5>(u, uf, E, gamma, op, st);
+        case 6: return launch_trace<6>(u, uf, E, gamma, op, st);
+        case 7: return launch_trace<7>(u, uf, E, gamma, op, st);
+        case 8: return launch_trace<8>(u, uf, E, gamma, op, st);
+        case 9: return launch_trace<9>(u, uf, E, gamma, op, st);
+        case 10: return launch_trace<10>(u, uf, E, gamma, op, st);
+        case 11: return launch_trace<11>(u, uf, E, gamma, op, st);
+        case 12: return launch_trace<12>(u, uf, E, gamma, op, st);
+        case 13: return launch_trace<13>(u, uf, E, gamma, op, st);
+        default: break;
+    }
+    set_error("the entropy trace is built for 2 <= n <= 13");
+    return SF_ERR_UNSUPPORTED;
+}
+
+}  // namespace sfhad

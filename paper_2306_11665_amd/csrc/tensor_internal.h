@@ -21,6 +21,10 @@ struct TensorRequest {
 
 int launch_tensor_apply(const TensorRequest &r);
 
+// Entropy-projected facet states of 3D Euler states (entropy_kernels.hip).
+int launch_entropy_trace(const double *u, double *uf, int64_t E, int n, double gamma, const Operator1D &op,
+                         hipStream_t stream);
+
 // Host modal basis on the nodes of a kind: V[q][k] = L_k(x_q) (orthonormal
 // Legendre) and its projection P = V^{-1}.
 bool build_basis(int n, int node_kind, double *V, double *P);

@@ -87,6 +87,8 @@ def lib() -> ctypes.CDLL:
             getattr(L, name).restype = ci
         L.sf_hadamard_volume_curvilinear.argtypes = [vp, vp, i64, ci, ci, vp, ctypes.POINTER(SfOpts)]
         L.sf_hadamard_volume_curvilinear.restype = ci
+        L.sf_entropy_trace.argtypes = [vp, i64, ci, vp, ctypes.POINTER(SfOpts)]
+        L.sf_entropy_trace.restype = ci
         L.sf_surface_operator_1d.argtypes = [ci, ci, _dp, _dp]
         L.sf_surface_operator_1d.restype = ci
         L.sf_basis_1d.argtypes = [ci, ci, _dp, _dp]
@@ -190,6 +192,21 @@ def volume_curvilinear(u, Ja, n: int, flux: str = "euler", *, nodes="gl", gamma=
     opts, keep = make_opts(nodes, "fp64", gamma, stream)
     check(lib().sf_hadamard_volume_curvilinear(u.data_ptr(), Ja.data_ptr(), E, n, FLUX[flux], out.data_ptr(),
                                                ctypes.byref(opts)), "sf_hadamard_volume_curvilinear")
+    del keep
+    return out
+
+
+def entropy_trace(u, n: int, *, nodes="gl", gamma=1.4, stream=None, out=None):
+    """Entropy-projected facet states (sf_entropy_trace): u (5, E, n^3) ->
+    (5, E, 6, n^2)."""
+    import torch
+    _check_tensor(u, "euler", n, 3)
+    E = u.shape[1]
+    out = torch.empty((5, E, 6, n * n), dtype=u.dtype, device=u.device) if out is None else out
+    if tuple(out.shape) != (5, E, 6, n * n) or not out.is_contiguous() or out.dtype != u.dtype:
+        raise ValueError("out must be a contiguous (5, E, 6, n^2) float64 tensor")
+    opts, keep = make_opts(nodes, "fp64", gamma, stream)
+    check(lib().sf_entropy_trace(u.data_ptr(), E, n, out.data_ptr(), ctypes.byref(opts)), "sf_entropy_trace")
     del keep
     return out
 

@@ -209,3 +209,18 @@ def test_curvilinear_validation(sf):
     o = sf.SfOpts(); L.sf_opts_init(ctypes.byref(o)); o.precision = 1
     assert f(BAD, BAD + 2 * big, 4, 4, 1, BAD + big, ctypes.byref(o)) == -2
     assert f(None, None, 0, 4, 1, None, None) == 0                    # E = 0
+
+
+def test_entropy_trace_validation(sf):
+    L = sf.lib()
+    f = L.sf_entropy_trace
+    big = 10 ** 9
+    assert f(None, 4, 4, None, None) == -1                   # null pointers
+    assert f(BAD, -1, 4, BAD + big, None) == -1               # negative E
+    assert f(BAD, 4, 14, BAD + big, None) == -2               # n <= 13
+    assert f(BAD, 4, 4, BAD + 8, None) == -1                  # overlap
+    o = sf.SfOpts(); L.sf_opts_init(ctypes.byref(o)); o.precision = 1
+    assert f(BAD, 4, 4, BAD + big, ctypes.byref(o)) == -2     # FP64 only
+    o = sf.SfOpts(); L.sf_opts_init(ctypes.byref(o)); o.gamma = 0.5
+    assert f(BAD, 4, 4, BAD + big, ctypes.byref(o)) == -1     # gamma
+    assert f(None, 0, 4, None, None) == 0                     # E = 0
