@@ -156,3 +156,47 @@ def test_poisson_load_on_simulated_device(serving):
         assert s["requests"] == 280
         assert 0 < s["p50_ms"] <= s["p99_ms"] <= s["max_ms"] < 1000
         assert srv.stats() == (0, 0, 0)
+
+
+def test_concurrent_clients_stress(serving):
+    """Four client threads submit, wait and release requests on random meshes
+    (registered and unregistered while others run) against a small budget:
+    the budget and the in-flight bound hold at every observation, every
+    request completes, and the server ends empty."""
+    import threading
+    budget = 6 * out_bytes(64, 4)
+    errors = []
+    with serving.Server(budget, max_inflight=5, sim_us_per_block=20.0) as srv:
+        base = [srv.register(tiny_state(16 * (k + 1), 4), 4) for k in range(4)]
+        lock = threading.Lock()
+
+        def client(seed):
+            rng = np.random.default_rng(seed)
+            try:
+                for it in range(40):
+                    m = base[rng.integers(len(base))]
+                    ts = [srv.submit(m.mesh_id, "fp64" if rng.random() < 0.5 else "fp32_split")
+                          for _ in range(int(rng.integers(1, 4)))]
+                    q, inflight, used = srv.stats()
+                    assert used <= budget and inflight <= 5, (used, inflight)
+                    for t in ts:
+                        srv.wait(t)
+                        srv.release(t)
+                    if it % 10 == 0:                         # a private mesh comes and goes
+                        with lock:
+                            extra = srv.register(tiny_state(8, 3), 3)
+                        t = srv.submit(extra.mesh_id)
+                        srv.wait(t)
+                        srv.release(t)
+                        srv.unregister(extra.mesh_id)
+            except Exception as e:                           # surfaced below
+                errors.append(e)
+
+        ths = [threading.Thread(target=client, args=(s,)) for s in range(4)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join(timeout=120)
+        assert not any(th.is_alive() for th in ths)
+        assert not errors, errors
+        assert srv.stats() == (0, 0, 0)
