@@ -199,8 +199,8 @@ def fig1_leg(torch, sfhad, W, stream) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-sample", type=int, default=4096, help="elements in the CPU-oracle sample")
     ap.add_argument("--no-extras", action="store_true", help="headline FP64 number only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
