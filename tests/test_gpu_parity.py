@@ -237,6 +237,33 @@ def test_empty_and_single_element(torch_dev, sf, orc):
     assert normwise(y, ref)[0].max() <= TOL64
 
 
+def test_large_ragged_mesh_sampled(torch_dev, sf, orc):
+    """A large element count that is not a multiple of anything (1,000,003
+    elements at n = 4, 16 elements per block: 2.6 GB in and out, 62,501 blocks
+    with a ragged last one): sampled elements, the last ones included,
+    against the dense oracle, in FP64 and FP32-split."""
+    torch = torch_dev
+    n, E = 4, 1_000_003
+    rng = np.random.default_rng(17)
+    from paper_2306_11665_amd import workloads as W
+    ut = torch.empty((5, E, n ** 3), dtype=torch.float64, device="cuda")
+    chunk = 200_000
+    for e0 in range(0, E, chunk):                      # generate in chunks (host memory)
+        k = min(chunk, E - e0)
+        ut[:, e0:e0 + k] = torch.from_numpy(W.euler_state(k, n, seed=int(rng.integers(1 << 30)),
+                                                          freestream_frac=0.1))
+    idx = np.unique(np.concatenate([rng.choice(E, 40, replace=False), np.arange(E - 16, E)]))
+    us = ut[:, idx].cpu().numpy()
+    ref = orc.dense_volume(us, n, 3, "euler")
+    for prec, tol in (("fp64", TOL64), ("fp32_split", TOL32)):
+        y = sf.volume(ut, n, 3, "euler", precision=prec)
+        torch.cuda.synchronize()
+        ys = y[:, idx].cpu().numpy()
+        mx, _ = normwise(ys, ref)
+        assert mx.max() <= tol, (prec, mx)
+        del y
+
+
 def test_bitwise_deterministic(torch_dev, sf):
     torch = torch_dev
     u = torch.from_numpy(state("euler", 2000, 8, 3, seed=700, fs=0.1)).cuda()
