@@ -116,13 +116,6 @@ __device__ __forceinline__ double rcp_fine(double x) {
     return __builtin_fma(r, __builtin_fma(e, e, e), r);
 }
 
-// 1/x to ~1e-14 relative: estimate plus one Newton step (only used where the
-// quotient feeds a correction term of size <= 1e-4 relative).
-__device__ __forceinline__ double rcp_coarse(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
-}
-
 // ln(1 + x) for finite x > -1, to about one ulp, without a library call.
 // 1 + x = u + e exactly (two-sum); u = 2^k m with m in [sqrt(1/2), sqrt(2));
 // ln(1 + x) = k ln 2 + ln m + e/u.  With f = m - 1 (exact) and s = f/(2 + f),
@@ -231,6 +224,7 @@ struct ScalarFlux {
 //   u = d^2/s^2 >= 1e-6:  N = d,      D = lr_a - lr_b  (a difference of
 //                         stored relative logarithms)
 //   u < 1e-6:             N = s^3/2,  D = s^2 + d^2 (1/3 + u/5),
+// (the switch is tested on |lr_a - lr_b| < 2e-3, which is |f| < tanh(1e-3)),
 //                         i.e. s^2 times the series of atanh(f)/f, f = d/s
 //                         (truncation u^3/7 < 1.5e-19; exact equality gives a).
 // The direct form's error, about eps (|ln(a/a_0)| + |ln(b/a_0)|) / |2f|, is
