@@ -519,6 +519,23 @@ def main() -> int:
         tsf = time.perf_counter() - t0
         result["cpu_sf_method"] = {"value": Es_ * n ** 3 * 5 / tsf, "unit": "DOF/s", "cores": cores,
                                    "elem_evals_per_s": Es_ / tsf}
+        # one core, on the first 64 sampled elements
+        oracle.set_num_threads(1)
+        try:
+            u1 = np.ascontiguousarray(us_np[:, :64, :])
+            t0 = time.perf_counter()
+            oracle.dense_volume(u1, n, 3, "euler")
+            t1c = time.perf_counter() - t0
+        finally:
+            oracle.set_num_threads(cores)
+        cpu_model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
+        result["cpu_baseline"].update({"one_core_elem_evals_per_s": 64 / t1c, "one_core_sample": "64 elements",
+                                       "cpu_model": cpu_model, "host_cpus": os.cpu_count()})
         y64 = out.cpu().numpy()[:, sample, :]
         err64 = normwise(y64, ref)
         result["fp64_error_vs_oracle"] = {"max": max(e[0] for e in err64), "per_variable": err64}
