@@ -214,9 +214,9 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(elements are independent, so the term shards by element range with no exchange, "
-              "but only the one-GPU kernel is built and measured)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(elements are independent, so the term would shard by element range with no exchange, "
+              "but only the one-GPU kernel is implemented and measured)", file=sys.stderr)
         return 2
 
     import torch
