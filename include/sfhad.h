@@ -270,13 +270,19 @@ int sf_server_create(size_t hbm_budget_bytes, int max_inflight, sf_server **out)
 int sf_server_create_sim(size_t hbm_budget_bytes, int max_inflight, double us_per_block,
                          sf_server **out);
 
+/* For tests of error handling, simulated servers only (SF_ERR_UNSUPPORTED
+ * otherwise): the next `count` batch launches fail as a failed HIP launch
+ * would, so their requests complete with SF_ERR_HIP from sf_wait. */
+int sf_server_sim_fail_launches(sf_server *srv, int count);
+
 /* Current queue length, requests holding output memory, and budget bytes in
  * use (any pointer may be NULL). */
 int sf_server_stats(sf_server *srv, int64_t *queued, int64_t *inflight, int64_t *budget_used);
 
 /* Register a mesh: the state (layout as above; Euler flux, d = 3,
- * 2 <= n <= 8) is copied to a device buffer the server owns.  u_host points
- * to host memory.  Returns SF_ERR_UNSUPPORTED for other fluxes or n. */
+ * 2 <= n <= 8, gamma = 1.4) is copied to a device buffer the server owns.
+ * u_host points to host memory.  Returns SF_ERR_UNSUPPORTED for other fluxes
+ * or n. */
 int sf_mesh_register(sf_server *srv, const double *u_host, int64_t elem_count, int n,
                      int flux_kind, int node_kind, sf_mesh *out);
 
@@ -289,7 +295,9 @@ int sf_poll(sf_server *srv, sf_ticket ticket);
 
 /* Block until the ticket completes; *y_dev points to the result (device,
  * owned by the server until sf_release), *latency_s is submit-to-completion
- * time on the host clock.  Either output pointer may be NULL. */
+ * time on the host clock.  Either output pointer may be NULL.  If the batch
+ * the request was in could not be launched, returns SF_ERR_HIP (detail in
+ * sf_last_error) with *y_dev = NULL; the ticket must still be released. */
 int sf_wait(sf_server *srv, sf_ticket ticket, const double **y_dev, double *latency_s);
 
 /* Return a completed ticket's output buffer to the budget. */

@@ -24,6 +24,7 @@
 // scheduler with a modelled service time and no device, for tests and
 // capacity planning.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -111,6 +112,7 @@ struct Request {
     int prec = 0;
     size_t off = 0, bytes = 0;
     State state = State::Queued;
+    int status = SF_OK;  // SF_ERR_HIP when its batch could not be launched
     Clock::time_point t_submit, t_done;
 };
 
@@ -126,6 +128,8 @@ public:
     virtual int launch(int s, const std::vector<ServeDesc> &descs) = 0;
     virtual bool done(int s) = 0;   // non-blocking
     virtual void drain(int s) = 0;  // blocking
+    // Make the next `count` launches fail (simulation only, for tests).
+    virtual int fail_launches(int) { return SF_ERR_UNSUPPORTED; }
 };
 
 class HipExecutor : public Executor {
@@ -322,6 +326,11 @@ public:
     }
     void mesh_free(double *) override {}
     int launch(int s, const std::vector<ServeDesc> &descs) override {
+        if (fail_.load() > 0) {
+            fail_--;
+            set_error("simulated launch failure");
+            return SF_ERR_HIP;
+        }
         int64_t blocks = 0;
         for (const ServeDesc &d : descs) blocks += d.nblk;
         const auto now = Clock::now();
@@ -332,8 +341,13 @@ public:
     }
     bool done(int s) override { return Clock::now() >= done_at_[s]; }
     void drain(int s) override { std::this_thread::sleep_until(done_at_[s]); }
+    int fail_launches(int count) override {
+        fail_ = count;
+        return SF_OK;
+    }
 
 private:
+    std::atomic<int> fail_{0};
     double us_;
     Clock::time_point busy_until_{}, done_at_[kSlots]{};
 };
@@ -435,6 +449,12 @@ public:
         }
         if (it == reqs_.end()) return fail(SF_ERR_NOT_FOUND, "unknown ticket");
         if (it->second.state != State::Done) return fail(SF_ERR_BUSY, "server stopping");
+        if (it->second.status != SF_OK) {
+            if (y) *y = nullptr;
+            if (latency)
+                *latency = std::chrono::duration<double>(it->second.t_done - it->second.t_submit).count();
+            return fail(it->second.status, "the request's batch could not be launched");
+        }
         if (y) {
             char *base = ex_->arena_base();
             *y = base ? reinterpret_cast<const double *>(base + it->second.off) : nullptr;
@@ -457,6 +477,8 @@ public:
         cv_.notify_all();
         return SF_OK;
     }
+
+    int fail_launches(int count) { return ex_->fail_launches(count); }
 
     // introspection for tests: queued, admitted-or-running, budget bytes in use
     void stats(int64_t *queued, int64_t *inflight, int64_t *used) {
@@ -518,7 +540,22 @@ private:
                 lk.unlock();
                 int st = ex_->launch(s, descs);
                 lk.lock();
-                if (st != SF_OK) launch_error_ = st;
+                if (st != SF_OK) {
+                    // the batch never ran: its requests complete with the error
+                    // (their output memory stays held until sf_release)
+                    launch_error_ = st;
+                    const auto now = Clock::now();
+                    for (int64_t t : slot_reqs_[s]) {
+                        auto it = reqs_.find(t);
+                        if (it != reqs_.end()) {
+                            it->second.state = State::Done;
+                            it->second.status = st;
+                            it->second.t_done = now;
+                        }
+                    }
+                    slot_reqs_[s].clear();
+                    slot_busy_[s] = false;
+                }
                 changed = true;
             }
         }
@@ -657,6 +694,13 @@ int sf_server_stats(sf_server *srv, int64_t *queued, int64_t *inflight, int64_t 
     if (!srv) return SF_ERR_ARG;
     srv->impl->stats(queued, inflight, budget_used);
     return SF_OK;
+}
+
+int sf_server_sim_fail_launches(sf_server *srv, int count) {
+    if (!srv || count < 0) return SF_ERR_ARG;
+    const int st = srv->impl->fail_launches(count);
+    if (st != SF_OK) sfhad::set_error("launch failures can only be injected into a simulated server");
+    return st;
 }
 
 int sf_server_destroy(sf_server *srv) {

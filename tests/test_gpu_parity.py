@@ -336,3 +336,44 @@ def test_library_is_the_path(torch_dev, sf):
     import ctypes
     maps = open("/proc/self/maps").read()
     assert os.path.realpath(sf.LIB_PATH) in maps
+
+
+def test_concurrent_host_threads_on_own_streams(torch_dev, sf):
+    """Four host threads call the library at once, each on its own stream and
+    with its own shapes (first calls of new (n, node kind) operators race in
+    the mutex-protected cache): every result equals the same call made alone."""
+    import threading
+    torch = torch_dev
+    assert sf.lib().sf_init(0, 8) == 0
+    cases = [(3, "gll", 0), (5, "gl", 1), (6, "gll", 2), (7, "gl", 3)]
+    inputs, alone = [], []
+    for n, kind, seed in cases:
+        u = torch.from_numpy(state("euler", 300, n, 3, seed=900 + seed, fs=0.1)).cuda()
+        inputs.append(u)
+    outs = [None] * len(cases)
+    errs = []
+
+    def worker(i):
+        try:
+            n, kind, _ = cases[i]
+            s = torch.cuda.Stream()
+            res = []
+            for _ in range(20):
+                res.append(sf.volume(inputs[i], n, 3, "euler", nodes=kind, stream=s))
+            s.synchronize()
+            outs[i] = res
+        except Exception as e:  # surfaced below
+            errs.append(e)
+
+    ths = [threading.Thread(target=worker, args=(i,)) for i in range(len(cases))]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join(timeout=120)
+    assert not errs, errs
+    torch.cuda.synchronize()
+    for i, (n, kind, _) in enumerate(cases):
+        ref = sf.volume(inputs[i], n, 3, "euler", nodes=kind)
+        torch.cuda.synchronize()
+        for r in outs[i]:
+            assert torch.equal(r, ref), (n, kind)

@@ -200,3 +200,25 @@ def test_concurrent_clients_stress(serving):
         assert not any(th.is_alive() for th in ths)
         assert not errors, errors
         assert srv.stats() == (0, 0, 0)
+
+
+def test_failed_batch_launch_reports_to_waiters(serving):
+    """A batch whose launch fails completes its requests with SF_ERR_HIP; they
+    are released normally and later batches run."""
+    import ctypes
+    L = serving._lib()
+    L.sf_server_sim_fail_launches.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    with serving.Server(1 << 30, max_inflight=8, sim_us_per_block=50.0) as srv:
+        m = srv.register(tiny_state(16, 4), 4)
+        assert L.sf_server_sim_fail_launches(srv._h, 1) == 0
+        bad = [srv.submit(m.mesh_id) for _ in range(2)]
+        for t in bad:
+            with pytest.raises(sfhad.SFError) as e:
+                srv.wait(t)
+            assert e.value.status == -3 and "launched" in str(e.value)
+            srv.release(t)
+        good = srv.submit(m.mesh_id)
+        srv.wait(good)
+        srv.release(good)
+        assert srv.stats() == (0, 0, 0)
+    assert L.sf_server_sim_fail_launches(None, 1) == -1
