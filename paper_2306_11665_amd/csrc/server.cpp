@@ -44,7 +44,7 @@ namespace serve {
 using Clock = std::chrono::steady_clock;
 
 constexpr size_t kAlign = 256;
-constexpr int kSlots = 2;
+constexpr int kSlots = 2;  // 3 and 4 measured no better (p50/p99 within run-to-run spread)
 constexpr int kGridCap = 1024;  // persistent workgroups per variant node
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -585,7 +585,7 @@ private:
                 cv_.notify_all();
                 continue;
             }
-            const bool busy = slot_busy_[0] || slot_busy_[1];
+            const bool busy = std::any_of(slot_busy_, slot_busy_ + kSlots, [](bool b) { return b; });
             if (busy) {
                 // a batch is running: poll its completion without holding the lock
                 lk.unlock();
@@ -613,7 +613,7 @@ private:
     std::deque<int64_t> queue_;
     std::vector<int64_t> pending_;
     std::vector<int64_t> slot_reqs_[kSlots];
-    bool slot_busy_[kSlots] = {false, false};
+    bool slot_busy_[kSlots] = {};
 };
 
 }  // namespace serve
