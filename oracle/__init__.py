@@ -65,6 +65,9 @@ def lib():
         L.oracle_basis_sparse.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ip, ip, dp]
         L.oracle_basis_1d.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
         L.oracle_tensor_apply.argtypes = [dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
+        L.oracle_tensor_apply_rect.argtypes = [dp, ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int, dp, dp]
+        L.oracle_basis_rect.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
         L.oracle_entropy_vars.argtypes = [dp, ctypes.c_double, dp]
         L.oracle_entropy_vars.restype = None
         L.oracle_conserved_from_entropy.argtypes = [dp, ctypes.c_double, dp]
@@ -199,15 +202,26 @@ def basis_1d(n: int, kind: str = "gl"):
 
 
 def tensor_apply(u, n: int, d: int, M) -> np.ndarray:
-    """out[v, e] = (M kron ... kron M) u[v, e] (d factors), u of shape (nvar, E, n^d)."""
+    """out[v, e] = (M kron ... kron M) u[v, e] (d factors), u of shape
+    (nvar, E, n^d); M is (n_out, n) (square or rectangular), out (nvar, E, n_out^d)."""
     u = np.ascontiguousarray(u, dtype=np.float64)
     M = np.ascontiguousarray(M, dtype=np.float64)
-    if u.ndim != 3 or u.shape[2] != n ** d or M.shape != (n, n):
+    if u.ndim != 3 or u.shape[2] != n ** d or M.ndim != 2 or M.shape[1] != n:
         raise ValueError("shape mismatch")
-    out = np.zeros_like(u)
-    if lib().oracle_tensor_apply(_dp(u), u.shape[1], n, d, u.shape[0], _dp(M), _dp(out)) != 0:
+    n_out = M.shape[0]
+    out = np.zeros((u.shape[0], u.shape[1], n_out ** d))
+    if lib().oracle_tensor_apply_rect(_dp(u), u.shape[1], n, n_out, d, u.shape[0], _dp(M), _dp(out)) != 0:
         raise ValueError("oracle rejected arguments")
     return out
+
+
+def basis_rect(n: int, m: int, kind: str = "gl"):
+    """(V, P): n orthonormal Legendre modes on m nodes (m x n) and the L2
+    projection P = (V^T W V)^{-1} V^T W (n x m)."""
+    V = np.zeros((m, n)); P = np.zeros((n, m))
+    if lib().oracle_basis_rect(n, m, NODES[kind], _dp(V), _dp(P)) != 0:
+        raise ValueError("bad arguments")
+    return V, P
 
 
 def entropy_vars(u, gamma: float = 1.4) -> np.ndarray:

@@ -503,37 +503,97 @@ int oracle_basis_1d(int n, int kind, double *V, double *P)
 }
 
 /* out_e = (M (x) ... (x) M) in_e for every element and variable: the d-fold
- * Kronecker power of the 1D matrix M (n x n, row-major), built explicitly
- * (n^d x n^d, z (x) y (x) x so that node ix + n iy + n^2 iz is the row
- * index) and applied as a dense matrix-vector product.  With M = V this is
- * the modal-to-nodal transformation u = chi(xi) u_hat; with M = P the
- * projection back.  Same layout as the volume term; nvar variables. */
-int oracle_tensor_apply(const double *in, long E, int n, int d, int nvar, const double *M, double *out)
+ * Kronecker power of the 1D matrix M (n_out x n_in, row-major), built
+ * explicitly (n_out^d x n_in^d, z (x) y (x) x so that node ix + n iy + n^2 iz
+ * is the row index) and applied as a dense matrix-vector product.  With
+ * M = V this is the modal-to-nodal transformation u = chi(xi) u_hat; with
+ * M = P the projection back; n_out != n_in maps between n modes and a
+ * different number of quadrature nodes.  Slab layout [v][e][node]: the input
+ * has n_in^d values per slab, the output n_out^d. */
+int oracle_tensor_apply_rect(const double *in, long E, int n_in, int n_out, int d, int nvar, const double *M,
+                             double *out)
 {
-    if (!in || !out || !M || E < 0 || n < 1 || d < 1 || d > 3 || nvar < 1) return -1;
-    int N = 1;
-    for (int k = 0; k < d; ++k) N *= n;
-    double *K = (double *)malloc(sizeof(double) * (size_t)N * N);
-    double *tmp = (double *)malloc(sizeof(double) * (size_t)N * N);
-    int size = n;
-    memcpy(K, M, sizeof(double) * n * n);
+    if (!in || !out || !M || E < 0 || n_in < 1 || n_out < 1 || d < 1 || d > 3 || nvar < 1) return -1;
+    int NI = 1, NO = 1;
+    for (int k = 0; k < d; ++k) { NI *= n_in; NO *= n_out; }
+    double *K = (double *)malloc(sizeof(double) * (size_t)NO * NI);
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)NO * NI);
+    int rows = n_out, cols = n_in;
+    memcpy(K, M, sizeof(double) * n_out * n_in);
     for (int k = 1; k < d; ++k) {
-        kron(K, size, size, M, n, n, tmp);
-        size *= n;
-        memcpy(K, tmp, sizeof(double) * (size_t)size * size);
+        kron(K, rows, cols, M, n_out, n_in, tmp);
+        rows *= n_out;
+        cols *= n_in;
+        memcpy(K, tmp, sizeof(double) * (size_t)rows * cols);
     }
     free(tmp);
 #pragma omp parallel for schedule(static)
     for (long ev = 0; ev < E * nvar; ++ev) {
-        const double *x = in + (size_t)ev * N;
-        double *y = out + (size_t)ev * N;
-        for (int i = 0; i < N; ++i) {
+        const double *x = in + (size_t)ev * NI;
+        double *y = out + (size_t)ev * NO;
+        for (int i = 0; i < NO; ++i) {
             double s = 0.0;
-            for (int j = 0; j < N; ++j) s += K[(size_t)i * N + j] * x[j];
+            for (int j = 0; j < NI; ++j) s += K[(size_t)i * NI + j] * x[j];
             y[i] = s;
         }
     }
     free(K);
+    return 0;
+}
+
+int oracle_tensor_apply(const double *in, long E, int n, int d, int nvar, const double *M, double *out)
+{
+    return oracle_tensor_apply_rect(in, E, n, n, d, nvar, M, out);
+}
+
+/* Modal basis on m quadrature nodes for n modes (m x n) and its L2 projection
+ * P = (V^T W V)^{-1} V^T W (n x m), the inverse of the mass matrix by
+ * Gauss-Jordan elimination.  P V = I for any m >= n. */
+int oracle_basis_rect(int n, int m, int kind, double *V, double *P)
+{
+    if (n < 1 || m < n || m > 64 || !V || !P) return -1;
+    double x[64], w[64];
+    if (oracle_nodes(m, kind, x, w) != 0) return -1;
+    for (int q = 0; q < m; ++q)
+        for (int k = 0; k < n; ++k) {
+            double Pk, dPk;
+            legendre(k, x[q], &Pk, &dPk);
+            V[q * n + k] = sqrt((2.0 * k + 1.0) / 2.0) * Pk;
+        }
+    /* [G | V^T W] with G = V^T W V, reduced to [I | P] */
+    const int c2 = n + m;
+    double *aug = (double *)calloc((size_t)n * c2, sizeof(double));
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) {
+            double g = 0.0;
+            for (int q = 0; q < m; ++q) g += V[q * n + i] * w[q] * V[q * n + j];
+            aug[i * c2 + j] = g;
+        }
+        for (int q = 0; q < m; ++q) aug[i * c2 + n + q] = V[q * n + i] * w[q];
+    }
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < n; ++i)
+            if (fabs(aug[i * c2 + c]) > fabs(aug[piv * c2 + c])) piv = i;
+        if (aug[piv * c2 + c] == 0.0) { free(aug); return -1; }
+        if (piv != c)
+            for (int j = 0; j < c2; ++j) {
+                double t = aug[c * c2 + j];
+                aug[c * c2 + j] = aug[piv * c2 + j];
+                aug[piv * c2 + j] = t;
+            }
+        double dd = aug[c * c2 + c];
+        for (int j = 0; j < c2; ++j) aug[c * c2 + j] /= dd;
+        for (int i = 0; i < n; ++i) {
+            if (i == c) continue;
+            double f = aug[i * c2 + c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < c2; ++j) aug[i * c2 + j] -= f * aug[c * c2 + j];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int q = 0; q < m; ++q) P[i * m + q] = aug[i * c2 + n + q];
+    free(aug);
     return 0;
 }
 

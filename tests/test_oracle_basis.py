@@ -93,3 +93,49 @@ def test_kronecker_power_tiny_brute_force(orc):
         3 * 3 * a + 5 * 3 * b + 3 * 5 * c + 5 * 5 * dd,      # (1, 1)
     ]
     assert np.array_equal(out, np.array(expect))
+
+
+@pytest.mark.parametrize("n,m,d", [(3, 5, 2), (4, 6, 3), (5, 8, 3), (8, 12, 3)])
+@pytest.mark.parametrize("kind", ["gl", "gll"])
+def test_modal_to_more_quadrature_nodes(orc, n, m, d, kind):
+    """n modes evaluated on m > n nodes (over-integration): the rectangular
+    Kronecker power reproduces the polynomial at the m-node grid (numpy's
+    legval2d/legval3d), and the L2 projection returns the coefficients."""
+    rng = np.random.default_rng(n * 13 + m + d)
+    V, P = orc.basis_rect(n, m, kind)
+    x, w = orc.nodes(m, kind)
+    ref_V = npleg.legvander(x, n - 1) * norms(n)[None, :]
+    assert np.abs(V - ref_V).max() < 1e-13 * max(1.0, np.abs(ref_V).max())
+    # the quadrature of m >= n + 1 nodes integrates the mass matrix exactly: P = V^T W
+    assert np.abs(P - V.T @ np.diag(w)).max() < 1e-12
+    uh = rng.uniform(-1, 1, (2, 3, n ** d))
+    u = orc.tensor_apply(uh, n, d, V)
+    assert u.shape == (2, 3, m ** d)
+    s = norms(n)
+    for v in range(2):
+        for e in range(3):
+            if d == 2:
+                c = uh[v, e].reshape(n, n).T * s[:, None] * s[None, :]
+                gx, gy = np.meshgrid(x, x, indexing="xy")
+                ref = npleg.legval2d(gx.ravel(), gy.ravel(), c)
+            else:
+                c = uh[v, e].reshape(n, n, n).transpose(2, 1, 0) * s[:, None, None] * s[None, :, None] * s[None, None, :]
+                gz, gy, gx = np.meshgrid(x, x, x, indexing="ij")
+                ref = npleg.legval3d(gx.ravel(), gy.ravel(), gz.ravel(), c)
+            assert np.abs(u[v, e] - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
+    back = orc.tensor_apply(u, m, d, P)
+    assert np.abs(back - uh).max() < 1e-12
+
+
+def test_rectangular_kronecker_tiny_brute_force(orc):
+    # n_in = 2, n_out = 3, d = 2: out[i + 3 j] = sum_{k, l} M[i][k] M[j][l] in[k + 2 l]
+    M = np.array([[1.0, 2.0], [3.0, 5.0], [7.0, 11.0]])
+    u = np.array([[[2.0, 3.0, 5.0, 7.0]]])
+    out = orc.tensor_apply(u, 2, 2, M)[0, 0]
+    expect = np.zeros(9)
+    for i in range(3):
+        for j in range(3):
+            for k in range(2):
+                for l in range(2):
+                    expect[i + 3 * j] += M[i, k] * M[j, l] * u[0, 0, k + 2 * l]
+    assert np.array_equal(out, expect)
