@@ -226,6 +226,21 @@ int sf_basis_1d(int n, int node_kind, double *V_host, double *P_host);
 int sf_tensor_apply(const double *in, int64_t elem_count, int n, int d, int nvar,
                     const double *M_host, double *out, void *stream);
 
+/* The same with a rectangular 1D matrix: M_host is n_out x n_in (row-major),
+ * e.g. n modes to m quadrature nodes (over-integration) or the projection
+ * back; in has n_in^d and out n_out^d doubles per (variable, element) slab,
+ * layouts as above.  2 <= n_in, n_out <= 16; in place only when
+ * n_in == n_out.  sf_tensor_apply is the n_in == n_out case. */
+int sf_tensor_apply_rect(const double *in, int64_t elem_count, int n_in, int n_out, int d, int nvar,
+                         const double *M_host, double *out, void *stream);
+
+/* n_modes orthonormal Legendre modes on the m_nodes nodes of node_kind:
+ * V_host (m_nodes x n_modes) and the L2 projection P_host
+ * = (V^T W V)^{-1} V^T W (n_modes x m_nodes), with P V = I; for
+ * m_nodes > n_modes the rule integrates the mass matrix exactly and
+ * P = V^T W.  2 <= n_modes <= m_nodes <= 16.  Either pointer may be NULL. */
+int sf_basis_rect(int n_modes, int m_nodes, int node_kind, double *V_host, double *P_host);
+
 /* Select the HIP device for the calling thread and build the operators for
  * every n up to n_max (optional warm-up; the first call per shape otherwise
  * does it).  Returns SF_ERR_HIP when no device is usable. */

@@ -274,36 +274,52 @@ int sf_basis_1d(int n, int node_kind, double *V, double *P) {
     return SF_OK;
 }
 
-int sf_tensor_apply(const double *in, int64_t E, int n, int d, int nvar, const double *M_host, double *out,
-                    void *stream) {
+int sf_tensor_apply_rect(const double *in, int64_t E, int n_in, int n_out, int d, int nvar, const double *M_host,
+                         double *out, void *stream) {
     if (E < 0) return fail(SF_ERR_ARG, "elem_count must be >= 0");
-    if (n < 1) return fail(SF_ERR_ARG, "n must be >= 1");
+    if (n_in < 1 || n_out < 1) return fail(SF_ERR_ARG, "n_in and n_out must be >= 1");
     if (d < 1) return fail(SF_ERR_ARG, "d must be >= 1");
     if (nvar < 1) return fail(SF_ERR_ARG, "nvar must be >= 1");
     if (!M_host) return fail(SF_ERR_ARG, "null M_host");
     if (d > 3 || d == 1) return fail(SF_ERR_UNSUPPORTED, "d must be 2 or 3");
-    if (n < SF_MIN_N || n > SF_MAX_N) return fail(SF_ERR_UNSUPPORTED, "n outside [2, 16]");
-    const int64_t N = ipow(n, d);
+    if (n_in < SF_MIN_N || n_in > SF_MAX_N || n_out < SF_MIN_N || n_out > SF_MAX_N)
+        return fail(SF_ERR_UNSUPPORTED, "n_in and n_out must be in [2, 16]");
+    const int64_t NI = ipow(n_in, d), NO = ipow(n_out, d);
+    const int64_t N = NI > NO ? NI : NO;
     if (E > 0 && E > INT64_MAX / (N * nvar * (int64_t)sizeof(double)))
         return fail(SF_ERR_ARG, "elem_count too large");
-    for (int i = 0; i < n * n; ++i)
+    for (int i = 0; i < n_in * n_out; ++i)
         if (!std::isfinite(M_host[i])) return fail(SF_ERR_ARG, "M_host has a non-finite entry");
     if (E == 0) return SF_OK;
     if (!in || !out) return fail(SF_ERR_ARG, "null in or out");
-    const size_t bytes = (size_t)(N * nvar * E) * sizeof(double);
-    const char *ib = reinterpret_cast<const char *>(in), *ob = reinterpret_cast<const char *>(out);
-    if (ib != ob && ib < ob + bytes && ob < ib + bytes)
-        return fail(SF_ERR_ARG, "out partially overlaps in (only in == out is allowed)");
+    const size_t ibytes = (size_t)(NI * nvar * E) * sizeof(double), obytes = (size_t)(NO * nvar * E) * sizeof(double);
+    if (!(in == out && n_in == n_out) && overlaps(in, ibytes, out, obytes))
+        return fail(SF_ERR_ARG, "out overlaps in (in place needs n_in == n_out and out == in)");
     TensorRequest r;
     r.in = in;
     r.out = out;
     r.E = E;
-    r.n = n;
+    r.n = n_in;
+    r.n_out = n_out;
     r.d = d;
     r.nvar = nvar;
     r.stream = reinterpret_cast<hipStream_t>(stream);
-    for (int i = 0; i < n * n; ++i) r.M[i] = M_host[i];
+    for (int i = 0; i < n_in * n_out; ++i) r.M[i] = M_host[i];
     return launch_tensor_apply(r);
+}
+
+int sf_tensor_apply(const double *in, int64_t E, int n, int d, int nvar, const double *M_host, double *out,
+                    void *stream) {
+    return sf_tensor_apply_rect(in, E, n, n, d, nvar, M_host, out, stream);
+}
+
+int sf_basis_rect(int n_modes, int m_nodes, int node_kind, double *V, double *P) {
+    if (n_modes < 1 || m_nodes < n_modes) return fail(SF_ERR_ARG, "need 1 <= n_modes <= m_nodes");
+    if (node_kind != SF_NODES_GAUSS_LEGENDRE && node_kind != SF_NODES_GAUSS_LOBATTO)
+        return fail(SF_ERR_ARG, "unknown node_kind");
+    if (n_modes < SF_MIN_N || m_nodes > SF_MAX_N) return fail(SF_ERR_UNSUPPORTED, "sizes outside [2, 16]");
+    if (!build_basis_rect(n_modes, m_nodes, node_kind, V, P)) return fail(SF_ERR_UNSUPPORTED, "basis construction failed");
+    return SF_OK;
 }
 
 const char *sf_status_string(int status) {

@@ -215,4 +215,27 @@ bool build_basis(int n, int node_kind, double *V, double *P) {
     return true;
 }
 
+// n modes on m > n nodes: V[q][k] = L_k(x_q) (m x n); the m-point rule
+// integrates the mass matrix exactly (degree 2n - 2 <= 2m - 3), so
+// V^T W V = I and the L2 projection is P = V^T W (n x m).
+bool build_basis_rect(int n, int m, int node_kind, double *V, double *P) {
+    if (m == n) return build_basis(n, node_kind, V, P);
+    if (m < n) return false;
+    Operator1D op;
+    if (!get_operator(m, node_kind, op)) return false;
+    for (int q = 0; q < m; ++q) {
+        const double x = op.x[q];
+        double pkm1 = 0.0, pk = 1.0;
+        for (int k = 0; k < n; ++k) {
+            const double v = std::sqrt((2.0 * k + 1.0) / 2.0) * pk;
+            if (V) V[q * n + k] = v;
+            if (P) P[k * m + q] = v * op.w[q];
+            const double pkp1 = ((2.0 * k + 1.0) * x * pk - k * pkm1) / (k + 1.0);
+            pkm1 = pk;
+            pk = pkp1;
+        }
+    }
+    return true;
+}
+
 }  // namespace sfhad

@@ -21,6 +21,7 @@
 // 128-byte segments).  One buffer instead of two doubles the blocks, and so
 // the loads in flight, per CU.  A block only writes the slabs it read, after
 // a barrier, so in == out is allowed.
+#include "kernels_common.h"
 #include "tensor_internal.h"
 
 namespace sfhad {
@@ -191,13 +192,167 @@ int dispatch_tensor(const TensorRequest &r) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Rectangular form: M is n_out x n_in (n modes to m quadrature nodes or
+// back), sizes at run time (2 <= n_in, n_out <= 16).  Pass m turns extent
+// n_in into n_out along direction m, so the intermediate stages have mixed
+// extents (directions before m already n_out); each stage is stored with x
+// fastest and one pad slot per x-row.  Same MFMA scheme and in-place single
+// buffer as the square kernel; the A operand rows q < n_out, k < n_in.
+struct RectArgs {
+    const double *in;
+    double *out;
+    int64_t slabs;
+    int ni, no, G, cap;  // sizes, slabs per block, LDS doubles per slab
+    double M[kMaxN * kMaxN];  // row-major n_out x n_in (row stride n_in)
+};
+
+template <int DIM>
+__global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectArgs) {
+    extern __shared__ double buf[];
+    const auto A = kernel_args<RectArgs>();
+    const int ni = A->ni, no = A->no, G = A->G, cap = A->cap;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int nin = 1, nout = 1;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        nin *= ni;
+        nout *= no;
+    }
+    const int64_t s0 = (int64_t)blockIdx.x * G;
+    const int gs = (int)((A->slabs - s0) < G ? (A->slabs - s0) : G);
+    const double *src = A->in + s0 * nin;
+    // stage 0: the input slabs, x fastest, one pad per x-row of n_in
+    for (int i = tid; i < gs * nin; i += kTensorThreads) {
+        const int g = i / nin, lin = i - g * nin;
+        buf[g * cap + lin + lin / ni] = src[i];
+    }
+    const int q_a = lane & 15, kq = lane >> 4;
+    double a[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = 4 * s + kq;
+        a[s] = (q_a < no && k < ni) ? A->M[q_a * ni + k] : 0.0;
+    }
+    const int ks = (ni + 3) >> 2;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+        // extents at stage m (before the pass) and stage m + 1 (after)
+        int ext[3], exo[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            ext[k] = k < DIM ? (k < m ? no : ni) : 1;
+            exo[k] = k < DIM ? (k <= m ? no : ni) : 1;
+        }
+        int lps = 1;  // lines per slab
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+            if (k != m) lps *= ext[k];
+        const int nlines = gs * lps;
+        const int tiles = (nlines + 15) >> 4;
+        d4 acc[4];
+        int cz[4][3];
+        int gg[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = wave + 4 * u;  // wave-uniform
+            acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+            ok[u] = false;
+            if (t >= tiles) continue;
+            const int Lg = t * 16 + (lane & 15);
+            ok[u] = Lg < nlines;
+            const int g = ok[u] ? Lg / lps : 0;
+            int L = ok[u] ? Lg - g * lps : 0;
+            gg[u] = g;
+            // coordinates of the other directions, increasing order, first fastest
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (k == m || k >= DIM) {
+                    cz[u][k] = 0;
+                    continue;
+                }
+                cz[u][k] = L % ext[k];
+                L /= ext[k];
+            }
+            for (int s = 0; s < ks; ++s) {
+                const int k = 4 * s + kq;
+                double b = 0.0;
+                if (ok[u] && k < ni) {
+                    int c[3] = {cz[u][0], cz[u][1], cz[u][2]};
+                    c[m] = k;
+                    const int lin = c[0] + ext[0] * (c[1] + ext[1] * c[2]);
+                    b = buf[g * cap + lin + lin / ext[0]];
+                }
+                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b, acc[u], 0, 0, 0);
+            }
+        }
+        if (m < DIM - 1) __syncthreads();  // every read of this pass is done
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (!ok[u]) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int q = 4 * r + kq;
+                if (q >= no) continue;
+                int c[3] = {cz[u][0], cz[u][1], cz[u][2]};
+                c[m] = q;
+                const int lin = c[0] + exo[0] * (c[1] + exo[1] * c[2]);
+                if (m == DIM - 1)
+                    A->out[(s0 + gg[u]) * nout + lin] = acc[u][r];
+                else
+                    buf[gg[u] * cap + lin + lin / exo[0]] = acc[u][r];
+            }
+        }
+        if (m < DIM - 1) __syncthreads();
+    }
+}
+
 }  // namespace dev
 
 int launch_tensor_apply(const TensorRequest &r) {
+    if (r.n_out != r.n) return launch_tensor_rect(r);
     if (r.d == 2) return dev::dispatch_tensor<2>(r);
     if (r.d == 3) return dev::dispatch_tensor<3>(r);
     set_error("d must be 2 or 3");
     return SF_ERR_UNSUPPORTED;
+}
+
+int launch_tensor_rect(const TensorRequest &r) {
+    using namespace dev;
+    const int mx = r.n > r.n_out ? r.n : r.n_out;
+    int mxd = 1, mxl = 1;
+    for (int k = 0; k < r.d; ++k) mxd *= mx;
+    mxl = mxd / mx;
+    int G = 2048 / mxd;
+    if (256 / mxl < G) G = 256 / mxl;
+    if (G < 1) G = 1;
+    RectArgs a;
+    a.in = r.in;
+    a.out = r.out;
+    a.slabs = r.E * r.nvar;
+    a.ni = r.n;
+    a.no = r.n_out;
+    a.G = G;
+    a.cap = mxd + mxl;
+    for (int i = 0; i < r.n_out * r.n; ++i) a.M[i] = r.M[i];
+    const int64_t blocks = (a.slabs + G - 1) / G;
+    if (blocks > 0x7fffffffLL) {
+        set_error("too many elements for one launch");
+        return SF_ERR_UNSUPPORTED;
+    }
+    const size_t lds = sizeof(double) * (size_t)G * a.cap;
+    if (r.d == 2)
+        hipLaunchKernelGGL(tensor_rect_kernel<2>, dim3((unsigned)blocks), dim3(kTensorThreads), lds, r.stream, a);
+    else
+        hipLaunchKernelGGL(tensor_rect_kernel<3>, dim3((unsigned)blocks), dim3(kTensorThreads), lds, r.stream, a);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) {
+        set_error(std::string("tensor_rect_kernel launch: ") + hipGetErrorString(err));
+        return SF_ERR_HIP;
+    }
+    return SF_OK;
 }
 
 }  // namespace sfhad

@@ -95,6 +95,10 @@ def lib() -> ctypes.CDLL:
         L.sf_basis_1d.restype = ci
         L.sf_tensor_apply.argtypes = [vp, i64, ci, ci, ci, _dp, vp, vp]
         L.sf_tensor_apply.restype = ci
+        L.sf_tensor_apply_rect.argtypes = [vp, i64, ci, ci, ci, ci, _dp, vp, vp]
+        L.sf_tensor_apply_rect.restype = ci
+        L.sf_basis_rect.argtypes = [ci, ci, ci, _dp, _dp]
+        L.sf_basis_rect.restype = ci
         L.sf_diag_log1p.argtypes = [vp, i64, vp, vp]
         L.sf_diag_log1p.restype = ci
         L.sf_server_destroy.argtypes = [vp]
@@ -249,23 +253,35 @@ def basis_1d(n: int, nodes: str = "gl"):
     return V, P
 
 
+def basis_rect(n_modes: int, m_nodes: int, nodes: str = "gl"):
+    """(V, P): n_modes orthonormal Legendre modes on m_nodes nodes (m x n) and
+    the L2 projection (n x m) (host, FP64)."""
+    V = np.zeros((m_nodes, n_modes)); P = np.zeros((n_modes, m_nodes))
+    check(lib().sf_basis_rect(n_modes, m_nodes, NODES[nodes], V.ctypes.data_as(_dp), P.ctypes.data_as(_dp)),
+          "sf_basis_rect")
+    return V, P
+
+
 def tensor_apply(u, n: int, d: int, M, *, out=None, stream=None):
-    """out[v, e] = (M kron ... kron M) u[v, e] (sf_tensor_apply); u is a
-    contiguous float64 CUDA tensor (nvar, E, n^d); out may be u itself."""
+    """out[v, e] = (M kron ... kron M) u[v, e] (sf_tensor_apply_rect); u is a
+    contiguous float64 CUDA tensor (nvar, E, n^d), M is (n_out, n); out is
+    (nvar, E, n_out^d) and may be u itself when n_out == n."""
     import torch
     if not isinstance(u, torch.Tensor) or u.device.type != "cuda" or u.dtype != torch.float64:
         raise TypeError("u must be a float64 CUDA tensor")
     if not u.is_contiguous() or u.dim() != 3 or u.shape[2] != n ** d:
         raise ValueError(f"u must be a contiguous (nvar, E, {n ** d}) tensor, got {tuple(u.shape)}")
-    if out is None:
-        out = torch.empty_like(u)
-    elif out.shape != u.shape or out.dtype != u.dtype or not out.is_contiguous() or out.device != u.device:
-        raise ValueError("out must match u")
     Mh = np.ascontiguousarray(M, dtype=np.float64)
-    if Mh.shape != (n, n):
-        raise ValueError(f"M must be ({n}, {n})")
-    check(lib().sf_tensor_apply(u.data_ptr(), u.shape[1], n, d, u.shape[0], Mh.ctypes.data_as(_dp),
-                                out.data_ptr(), _stream_handle(stream)), "sf_tensor_apply")
+    if Mh.ndim != 2 or Mh.shape[1] != n:
+        raise ValueError(f"M must be (n_out, {n})")
+    n_out = Mh.shape[0]
+    shape = (u.shape[0], u.shape[1], n_out ** d)
+    if out is None:
+        out = torch.empty(shape, dtype=u.dtype, device=u.device)
+    elif tuple(out.shape) != shape or out.dtype != u.dtype or not out.is_contiguous() or out.device != u.device:
+        raise ValueError(f"out must be a contiguous float64 tensor {shape} on u's device")
+    check(lib().sf_tensor_apply_rect(u.data_ptr(), u.shape[1], n, n_out, d, u.shape[0], Mh.ctypes.data_as(_dp),
+                                     out.data_ptr(), _stream_handle(stream)), "sf_tensor_apply_rect")
     return out
 
 

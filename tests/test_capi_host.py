@@ -224,3 +224,26 @@ def test_entropy_trace_validation(sf):
     o = sf.SfOpts(); L.sf_opts_init(ctypes.byref(o)); o.gamma = 0.5
     assert f(BAD, 4, 4, BAD + big, ctypes.byref(o)) == -1     # gamma
     assert f(None, 0, 4, None, None) == 0                     # E = 0
+
+
+@pytest.mark.parametrize("n,m,kind", [(2, 3, "gl"), (4, 7, "gll"), (8, 12, "gl"), (5, 5, "gll"), (15, 16, "gl")])
+def test_basis_rect_matches_oracle(sf, orc, n, m, kind):
+    V, P = sf.basis_rect(n, m, kind)
+    Vo, Po = orc.basis_rect(n, m, kind)
+    assert np.abs(V - Vo).max() <= 1e-13 * max(1.0, np.abs(Vo).max())
+    assert np.abs(P - Po).max() <= 1e-12 * max(1.0, np.abs(Po).max())
+    assert np.abs(P @ V - np.eye(n)).max() < 1e-12
+
+
+def test_tensor_rect_validation(sf):
+    L = sf.lib()
+    M = np.ones((6, 4))
+    Mp = M.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    f = L.sf_tensor_apply_rect
+    big = 10 ** 9
+    assert f(BAD, 4, 4, 17, 3, 5, Mp, BAD + big, None) == -2      # n_out > 16
+    assert f(BAD, 4, 4, 0, 3, 5, Mp, BAD + big, None) == -1       # n_out < 1
+    assert f(BAD, 4, 4, 6, 3, 5, Mp, BAD, None) == -1             # in place needs n_in == n_out
+    assert f(None, 0, 4, 6, 3, 5, Mp, None, None) == 0            # E = 0
+    assert L.sf_basis_rect(5, 4, 0, None, None) == -1              # m < n
+    assert L.sf_basis_rect(4, 17, 0, None, None) == -2

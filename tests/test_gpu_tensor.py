@@ -132,3 +132,40 @@ def test_full_size_sampled_and_round_trip(torch_dev, sf, orc):
     uh_np = uh.cpu().numpy()
     ref = orc.tensor_apply(np.ascontiguousarray(u[:, idx, :]), n, d, P)
     assert relerr(uh_np[:, idx, :], ref) <= TOL
+
+
+@pytest.mark.parametrize("ni,no,d", [(3, 5, 2), (4, 6, 3), (5, 3, 3), (2, 16, 2), (8, 12, 3), (16, 9, 3),
+                                     (7, 8, 3), (4, 16, 3)])
+def test_rectangular_every_shape_class(torch_dev, sf, orc, ni, no, d):
+    """n_in != n_out (modes to more or fewer nodes): several blocks and a
+    ragged last one, a non-symmetric matrix, against the oracle."""
+    rng = np.random.default_rng(ni * 31 + no + d)
+    M = rng.normal(size=(no, ni))
+    nvar = 5
+    mx = max(ni, no)
+    G = max(1, min(2048 // mx ** d, 256 // mx ** (d - 1)))
+    slabs = 3 * G + 1
+    E = -(-slabs // nvar)
+    u = rng.normal(size=(nvar, E, ni ** d))
+    ref = orc.tensor_apply(u, ni, d, M)
+    y = gpu_apply(torch_dev, sf, u, ni, d, M)
+    assert y.shape == ref.shape
+    err = relerr(y, ref)
+    print(f"rect {ni}->{no} d={d}: {err:.2e}")
+    assert err <= TOL, err
+
+
+@pytest.mark.parametrize("n,m", [(4, 6), (8, 12), (5, 16)])
+@pytest.mark.parametrize("kind", ["gl", "gll"])
+def test_over_integration_round_trip(torch_dev, sf, orc, n, m, kind):
+    """n modes to m > n quadrature nodes and back with the library's basis:
+    the interpolation matches the oracle and the projection returns the
+    coefficients (P V = I)."""
+    V, P = sf.basis_rect(n, m, kind)
+    Vo, Po = orc.basis_rect(n, m, kind)
+    assert np.abs(V - Vo).max() < 1e-13 and np.abs(P - Po).max() < 1e-12
+    uh = modal(2, 37, n, 3, seed=n + m)
+    uq = gpu_apply(torch_dev, sf, uh, n, 3, V)
+    assert relerr(uq, orc.tensor_apply(uh, n, 3, V)) <= TOL
+    back = gpu_apply(torch_dev, sf, uq, m, 3, P)
+    assert np.abs(back - uh).max() <= 1e-12 * np.abs(uh).max()
