@@ -188,6 +188,16 @@ int sf_hadamard_volume_surface(const double *u_vol, const double *u_face, int64_
  * variables (v_4 < 0); nothing is checked on the device. */
 int sf_entropy_trace(const double *u_nodes, int64_t elem_count, int n, double *u_face, const sf_opts *opts);
 
+/* Pointwise maps between the conserved variables u = (rho, rho vel, E) and
+ * the entropy variables v = dU/du (U = -rho s/(gamma - 1)) of 3D Euler,
+ * over `count` states stored as 5 arrays of count doubles (in[k*count + i]):
+ * with the basis transformation they compose the entropy projection
+ * u(V P v(u)) on any node set (e.g. over-integrated volume nodes).  In place
+ * (out == in) is allowed; asynchronous on `stream` (NULL: null stream);
+ * states must be physical (rho, p > 0; v_4 < 0). */
+int sf_entropy_variables(const double *u, int64_t count, double *v, double gamma, void *stream);
+int sf_conserved_variables(const double *v, int64_t count, double *u, double gamma, void *stream);
+
 /* The Lagrange basis of the n nodes at the interval ends (host, FP64):
  * lm[k] = l_k(-1), lp[k] = l_k(+1); either may be NULL.  No GPU needed. */
 int sf_surface_operator_1d(int n, int node_kind, double *lm_host, double *lp_host);

@@ -218,6 +218,27 @@ int sf_entropy_trace(const double *u, int64_t E, int n, double *uf, const sf_opt
     return launch_entropy_trace(u, uf, E, n, o.gamma, op, reinterpret_cast<hipStream_t>(o.stream));
 }
 
+namespace {
+int entropy_map(const double *in, int64_t count, double *out, double gamma, void *stream, int dir) {
+    if (count < 0) return fail(SF_ERR_ARG, "count must be >= 0");
+    if (!(gamma > 1.0) || !std::isfinite(gamma)) return fail(SF_ERR_ARG, "gamma must be finite and > 1");
+    if (count == 0) return SF_OK;
+    if (!in || !out) return fail(SF_ERR_ARG, "null in or out");
+    if (count > INT64_MAX / (5 * (int64_t)sizeof(double))) return fail(SF_ERR_ARG, "count too large");
+    const size_t bytes = (size_t)count * 5 * sizeof(double);
+    if (in != out && overlaps(in, bytes, out, bytes)) return fail(SF_ERR_ARG, "out partially overlaps in");
+    return launch_entropy_map(in, out, count, gamma, dir, reinterpret_cast<hipStream_t>(stream));
+}
+}  // namespace
+
+int sf_entropy_variables(const double *u, int64_t count, double *v, double gamma, void *stream) {
+    return entropy_map(u, count, v, gamma, stream, 0);
+}
+
+int sf_conserved_variables(const double *v, int64_t count, double *u, double gamma, void *stream) {
+    return entropy_map(v, count, u, gamma, stream, 1);
+}
+
 int sf_surface_operator_1d(int n, int node_kind, double *lm, double *lp) {
     if (n < 1) return fail(SF_ERR_ARG, "n must be >= 1");
     if (node_kind != SF_NODES_GAUSS_LEGENDRE && node_kind != SF_NODES_GAUSS_LOBATTO)

@@ -117,6 +117,50 @@ int launch_trace(const double *u, double *uf, int64_t E, double gamma, const Ope
     return SF_OK;
 }
 
+// Pointwise maps over SoA arrays of `count` states (5 arrays of count
+// doubles): conserved -> entropy variables (dir = 0) or back (dir = 1).
+// Grid-stride, coalesced; for composing the entropy projection with the
+// basis transformation (u(V P v(u)) on any node set).
+__global__ void __launch_bounds__(256) entropy_map_kernel(const double *__restrict__ in, double *__restrict__ out,
+                                                         int64_t count, double g, int dir) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double x0 = in[i], x1 = in[count + i], x2 = in[2 * count + i], x3 = in[3 * count + i],
+                     x4 = in[4 * count + i];
+        double y0, y1, y2, y3, y4;
+        if (dir == 0) {
+            const double irho = 1.0 / x0;
+            const double vx = x1 * irho, vy = x2 * irho, vz = x3 * irho;
+            const double q = vx * vx + vy * vy + vz * vz;
+            const double p = (g - 1.0) * (x4 - 0.5 * x0 * q);
+            const double rp = x0 / p;
+            const double s = log(p) - g * log(x0);
+            y0 = (g - s) / (g - 1.0) - 0.5 * rp * q;
+            y1 = rp * vx;
+            y2 = rp * vy;
+            y3 = rp * vz;
+            y4 = -rp;
+        } else {
+            const double rp = -x4;
+            const double vx = x1 / rp, vy = x2 / rp, vz = x3 / rp;
+            const double q = vx * vx + vy * vy + vz * vz;
+            const double s = g - (g - 1.0) * (x0 + 0.5 * rp * q);
+            const double rho = exp((s + log(rp)) / (1.0 - g));
+            const double p = rho / rp;
+            y0 = rho;
+            y1 = rho * vx;
+            y2 = rho * vy;
+            y3 = rho * vz;
+            y4 = p / (g - 1.0) + 0.5 * rho * q;
+        }
+        out[i] = y0;
+        out[count + i] = y1;
+        out[2 * count + i] = y2;
+        out[3 * count + i] = y3;
+        out[4 * count + i] = y4;
+    }
+}
+
 }  // namespace dev
 
 int launch_entropy_trace(const double *u, double *uf, int64_t E, int n, double gamma, const Operator1D &op,
@@ -139,6 +183,18 @@ int launch_entropy_trace(const double *u, double *uf, int64_t E, int n, double g
     }
     set_error("the entropy trace is built for 2 <= n <= 13");
     return SF_ERR_UNSUPPORTED;
+}
+
+int launch_entropy_map(const double *in, double *out, int64_t count, double gamma, int dir, hipStream_t st) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(dev::entropy_map_kernel, dim3((unsigned)blocks), dim3(256), 0, st, in, out, count, gamma, dir);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) {
+        set_error(std::string("entropy_map_kernel launch: ") + hipGetErrorString(err));
+        return SF_ERR_HIP;
+    }
+    return SF_OK;
 }
 
 }  // namespace sfhad

@@ -27,6 +27,8 @@ int launch_tensor_rect(const TensorRequest &r);
 // Entropy-projected facet states of 3D Euler states (entropy_kernels.hip).
 int launch_entropy_trace(const double *u, double *uf, int64_t E, int n, double gamma, const Operator1D &op,
                          hipStream_t stream);
+// Pointwise conserved -> entropy variables (dir 0) or back (dir 1), 5 SoA arrays.
+int launch_entropy_map(const double *in, double *out, int64_t count, double gamma, int dir, hipStream_t stream);
 
 // Host modal basis on the nodes of a kind: V[q][k] = L_k(x_q) (orthonormal
 // Legendre) and its projection P = V^{-1}.

@@ -87,6 +87,9 @@ def lib() -> ctypes.CDLL:
             getattr(L, name).restype = ci
         L.sf_hadamard_volume_curvilinear.argtypes = [vp, vp, i64, ci, ci, vp, ctypes.POINTER(SfOpts)]
         L.sf_hadamard_volume_curvilinear.restype = ci
+        for name in ("sf_entropy_variables", "sf_conserved_variables"):
+            getattr(L, name).argtypes = [vp, i64, vp, ctypes.c_double, vp]
+            getattr(L, name).restype = ci
         L.sf_entropy_trace.argtypes = [vp, i64, ci, vp, ctypes.POINTER(SfOpts)]
         L.sf_entropy_trace.restype = ci
         L.sf_surface_operator_1d.argtypes = [ci, ci, _dp, _dp]
@@ -198,6 +201,29 @@ def volume_curvilinear(u, Ja, n: int, flux: str = "euler", *, nodes="gl", gamma=
                                                ctypes.byref(opts)), "sf_hadamard_volume_curvilinear")
     del keep
     return out
+
+
+def _entropy_map(name, x, gamma, stream, out):
+    import torch
+    if not isinstance(x, torch.Tensor) or x.device.type != "cuda" or x.dtype != torch.float64 \
+            or not x.is_contiguous() or x.shape[0] != 5:
+        raise ValueError("expected a contiguous float64 CUDA tensor with 5 leading components")
+    out = torch.empty_like(x) if out is None else out
+    if out.shape != x.shape or not out.is_contiguous() or out.dtype != x.dtype:
+        raise ValueError("out must match the input")
+    check(getattr(lib(), name)(x.data_ptr(), x.numel() // 5, out.data_ptr(), float(gamma), _stream_handle(stream)),
+          name)
+    return out
+
+
+def entropy_variables(u, *, gamma=1.4, stream=None, out=None):
+    """Entropy variables of conserved states u (5, ...) (sf_entropy_variables)."""
+    return _entropy_map("sf_entropy_variables", u, gamma, stream, out)
+
+
+def conserved_variables(v, *, gamma=1.4, stream=None, out=None):
+    """Conserved states of entropy variables v (5, ...) (sf_conserved_variables)."""
+    return _entropy_map("sf_conserved_variables", v, gamma, stream, out)
 
 
 def entropy_trace(u, n: int, *, nodes="gl", gamma=1.4, stream=None, out=None):

@@ -226,6 +226,19 @@ def test_entropy_trace_validation(sf):
     assert f(None, 0, 4, None, None) == 0                     # E = 0
 
 
+@pytest.mark.parametrize("name", ["sf_entropy_variables", "sf_conserved_variables"])
+def test_entropy_map_validation(sf, name):
+    f = getattr(sf.lib(), name)
+    big = 10 ** 9
+    assert f(BAD, -1, BAD + big, 1.4, None) == -1            # negative count
+    assert f(None, 4, BAD + big, 1.4, None) == -1            # null input
+    assert f(BAD, 4, BAD + 8, 1.4, None) == -1               # partial overlap
+    assert f(BAD, 4, BAD + big, 1.0, None) == -1             # gamma > 1
+    assert f(BAD, 4, BAD + big, float("nan"), None) == -1    # gamma finite
+    assert f(BAD, 2 ** 62, BAD + big, 1.4, None) == -1       # byte count overflows
+    assert f(None, 0, None, 1.4, None) == 0                  # count = 0
+
+
 @pytest.mark.parametrize("n,m,kind", [(2, 3, "gl"), (4, 7, "gll"), (8, 12, "gl"), (5, 5, "gll"), (15, 16, "gl")])
 def test_basis_rect_matches_oracle(sf, orc, n, m, kind):
     V, P = sf.basis_rect(n, m, kind)

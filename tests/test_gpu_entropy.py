@@ -86,3 +86,75 @@ def test_full_size_sampled(torch_dev, sf, orc):
     idx = np.sort(np.random.default_rng(14).choice(w.E, 32, replace=False))
     ref = orc.entropy_trace(np.ascontiguousarray(u[:, idx]), 8, "gll")
     assert relerr(y[:, idx], ref) <= TOL
+
+
+def physical_states(count, seed):
+    from paper_2306_11665_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.2, 3.0, count)
+    p = rng.uniform(0.2, 3.0, count)
+    vel = rng.uniform(-1.5, 1.5, (3, count))
+    return np.ascontiguousarray(W.primitives_to_conserved(rho, vel, p))
+
+
+@pytest.mark.parametrize("count", [1, 255, 256, 257, 100_003])
+def test_entropy_variable_maps(torch_dev, sf, orc, count):
+    """Pointwise u -> v and v -> u against the oracle's maps on sampled
+    states (every state when few), and the round trip on all of them;
+    counts around one block and a ragged multi-block one."""
+    torch = torch_dev
+    u = physical_states(count, seed=count)
+    ut = torch.from_numpy(u).cuda()
+    v = sf.entropy_variables(ut)
+    back = sf.conserved_variables(v)
+    torch.cuda.synchronize()
+    vn, bn = v.cpu().numpy(), back.cpu().numpy()
+    idx = np.arange(count) if count <= 300 else np.random.default_rng(1).choice(count, 300, replace=False)
+    for i in idx:
+        rv = orc.entropy_vars(u[:, i])
+        assert np.abs(vn[:, i] - rv).max() <= TOL * np.abs(rv).max(), i
+        ru = orc.conserved_from_entropy(vn[:, i])
+        assert np.abs(bn[:, i] - ru).max() <= TOL * np.abs(ru).max(), i
+    assert relerr(bn, u) <= 1e-12
+
+
+def test_entropy_variable_maps_in_place(torch_dev, sf):
+    torch = torch_dev
+    u = physical_states(1000, seed=4)
+    ut = torch.from_numpy(u).cuda()
+    v = sf.entropy_variables(ut)
+    w = ut.clone()
+    sf.entropy_variables(w, out=w)
+    sf.conserved_variables(w, out=w)
+    torch.cuda.synchronize()
+    assert relerr(w.cpu().numpy(), u) <= 1e-12
+    assert relerr(sf.entropy_variables(ut).cpu().numpy(), v.cpu().numpy()) == 0.0
+
+
+@pytest.mark.parametrize("n,m", [(4, 6), (6, 9)])
+def test_over_integrated_entropy_projection(torch_dev, sf, orc, n, m):
+    """The entropy projection on m > n over-integration nodes,
+    u(V P v(u)) with v projected from the n collocated nodes to modes and
+    evaluated on the m^3 nodes: the GPU chain (map, two basis
+    transformations, inverse map) against the oracle's chain."""
+    torch = torch_dev
+    E = 9
+    u = smooth_state(orc, E, n, "gl", seed=n * m)
+    _, Pn = orc.basis_rect(n, n, "gl")
+    Vm, _ = orc.basis_rect(n, m, "gl")
+    ut = torch.from_numpy(u).cuda()
+    v = sf.entropy_variables(ut)
+    vh = sf.tensor_apply(v, n, 3, Pn)
+    vq = sf.tensor_apply(vh, n, 3, Vm)
+    uq = sf.conserved_variables(vq)
+    torch.cuda.synchronize()
+    vo = np.zeros_like(u)
+    for e in range(E):
+        for k in range(n ** 3):
+            vo[:, e, k] = orc.entropy_vars(u[:, e, k])
+    vqo = orc.tensor_apply(orc.tensor_apply(vo, n, 3, Pn), n, 3, Vm)
+    uqo = np.zeros_like(vqo)
+    for e in range(E):
+        for k in range(m ** 3):
+            uqo[:, e, k] = orc.conserved_from_entropy(vqo[:, e, k])
+    assert relerr(uq.cpu().numpy(), uqo) <= TOL
