@@ -48,7 +48,7 @@ OPS_PER_DIAG = 25
 # profiled (same digest); otherwise the traffic is reported as unmeasured.
 TRAFFIC_PROFILE = os.path.join("profiles", "sf_volume_kernel_euler_n8_e32768.md")
 KERNEL_SOURCES = [os.path.join("paper_2306_11665_amd", "csrc", f)
-                  for f in ("volume_kernels.hip", "kernels_common.h", "sfhad_internal.h")] + \
+                  for f in ("volume_kernels.hip", "sf_block.h", "kernels_common.h", "sfhad_internal.h")] + \
                  [os.path.join("paper_2306_11665_amd", "build.py")]
 
 

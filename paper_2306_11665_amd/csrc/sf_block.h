@@ -1,0 +1,264 @@
+// The block-level machinery shared by the sum-factorized kernels (Eq. (3)
+// with the coefficients of Eq. (5)): the LDS layout, the operator views and
+// sf_block, which runs a block of elements through the steps below with a
+// per-line work policy (the volume pairs, the surface term, or both).
+//
+// One workgroup per block of EPB elements; d groups of LPD lanes, group m
+// handling every line of direction m of the block's elements, one line per
+// lane (at n = 8 in 3D: one element, 3 waves of 64 lanes, 64 lines each).
+//
+//   a1  stage:   coalesced SoA loads of the conserved state, conversion to
+//                the flux's per-node quantities, stored in LDS;
+//   a2  lines:   the lane's line = padded LDS base + a * stride (Algorithm 1
+//                as index arithmetic, nothing materialized);
+//   a3  coeffs:  Q[a][c] from the kernel arguments (scalar registers),
+//                w_perp once per line (Algorithm 2's values, on the fly);
+//   a4  flux:    every unordered pair (a < c) once plus the n diagonal
+//                physical fluxes;
+//   a5  reduce:  t_a += Q[a][c] F, t_c += Q[c][a] F in registers;
+//   a6  sum:     t * w_perp summed over the d directions in FP64 in LDS in the
+//                fixed order m = 0, 1, 2 (bit-reproducible), then coalesced
+//                stores.
+//   a7  the FP32-split form is the same kernel with the EulerFP32Split policy
+//                (FP32 inputs, flux and line sums; FP64 direction sum).
+#pragma once
+
+#include "kernels_common.h"
+#include "sfhad_internal.h"
+
+namespace sfhad {
+namespace dev {
+
+// a2..a5 for one line: every unordered pair (a < c) once plus the diagonal,
+// accumulated into t.  The loads of the stored arrays are rotated into the
+// frame of direction M.
+template <int N, class P, int M, class Op>
+__device__ __forceinline__ void line_pairs(const typename P::Real *le, int AS, int pbase, int pstride,
+                                           const Op &op, const typename P::Consts &K, double gamma,
+                                           typename P::Real (&t)[N][P::NV]) {
+    using R = typename P::Real;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        const typename P::Node A = P::load(le, AS, pin(pbase + a * pstride), M);
+        R F[P::NV];
+        P::diag(A, gamma, F);
+        const R qaa = (R)op.q(a * N + a);
+#pragma unroll
+        for (int k = 0; k < P::NV; ++k) t[a][k] = qaa * F[k] + t[a][k];
+#pragma unroll
+        for (int c = a + 1; c < N; ++c) {
+            // re-read node c from LDS for every pair: an opaque index stops
+            // the compiler from keeping the whole line live in registers
+            const typename P::Node C = P::load_partner(le, AS, pin(pbase + c * pstride), M);
+            P::pair(A, C, K, F);
+            const R qac = (R)op.q(a * N + c), qca = (R)op.q(c * N + a);
+#pragma unroll
+            for (int k = 0; k < P::NV; ++k) {
+                t[a][k] = qac * F[k] + t[a][k];
+                t[c][k] = qca * F[k] + t[c][k];
+            }
+            // one pair in flight at a time: its sums complete here, before
+            // the next pair's loads (ordered after this fence) are issued
+#pragma unroll
+            for (int k = 0; k < P::NV; ++k) {
+                t[a][k] = pin(t[a][k]);
+                t[c][k] = pin(t[c][k]);
+            }
+        }
+    }
+}
+
+// Distance between two stored arrays, in elements of size `bytes`: at least
+// `base`, padded so that consecutive arrays start 8 banks apart (the
+// unpadded n = 8 layout puts every array on the same bank).
+template <int bytes>
+constexpr int array_stride(int base) {
+    int as = base;
+    while (((as * bytes / 4) % 32) != 8) ++as;
+    return as;
+}
+
+// LDS needed by one block of the sum-factorized kernel: the staged inputs
+// (NS arrays of Real) and, after the compute phase, the FP64 outputs (NV
+// arrays of doubles, same stride) share the buffer.
+template <int N, int DIM, class P>
+struct SfLayout {
+    using G = Geom<N, DIM>;
+    using R = typename P::Real;
+    static constexpr int AS = array_stride<(int)sizeof(R)>(G::EPB * G::PADN);  // array distance (elements)
+    static constexpr int IN_D = (P::NS * AS * (int)sizeof(R) + 7) / 8;
+    static constexpr int OUT_D = P::NV * AS;
+    static constexpr int LDS_D = IN_D > OUT_D ? IN_D : OUT_D;  // doubles
+    static constexpr int NREF = P::NREF > 0 ? P::NREF : 1;
+    static constexpr int REF_D = G::EPB * NREF;                // doubles
+};
+
+// The 1D operator, read from the kernel arguments (standalone launches) or
+// from a device table (the serving kernel).  Both give the same values.
+template <int N>
+struct KernargOp {
+    kernarg_ptr<OpArg<N>> a;
+    __device__ double q(int i) const { return a->Q[i]; }
+    __device__ double w(int i) const { return a->w[i]; }
+};
+
+// The same through a reference to the by-value parameter: for the small
+// argument blocks (n <= 9) clang keeps it in the argument segment, and the
+// kernels come out slightly faster this way.
+template <int N>
+struct ParamOp {
+    const OpArg<N> &a;
+    __device__ double q(int i) const { return a.Q[i]; }
+    __device__ double w(int i) const { return a.w[i]; }
+};
+
+struct TableOp {
+    const double *__restrict__ Q;
+    const double *__restrict__ W;
+    // the base is made opaque at every read so that the (scalar) loads stay
+    // next to their use instead of being hoisted and held in registers
+    __device__ double q(int i) const {
+        const double *p = Q;
+        asm volatile("" : "+s"(p));
+        return p[i];
+    }
+    __device__ double w(int i) const { return W[i]; }
+};
+
+// The per-line work of a block.  VolumeWork is a2..a5 (every pair of the
+// line); SurfaceWork is the facet part of the surface term (below);
+// VolumeSurfaceWork does both into the same line sums.
+struct VolumeWork {
+    template <int M, int N, class P, class Op, class R>
+    __device__ __forceinline__ void lines(const R *le, int AS, int pbase, int pstride, const Op &op,
+                                          const typename P::Consts &K, double gamma, R (&t)[N][P::NV], int64_t,
+                                          int, double, const double *) const {
+        line_pairs<N, P, M>(le, AS, pbase, pstride, op, K, gamma, t);
+    }
+};
+
+// One block of EPB elements starting at element e0 of an E-element mesh:
+// steps a1..a6 with the line work of `work`.  lds holds SfLayout::LDS_D
+// doubles, sref SfLayout::REF_D.
+template <int N, int DIM, class P, class Op, class Work = VolumeWork>
+__device__ __forceinline__ void sf_block(const double *__restrict__ u, double *__restrict__ out, int64_t E,
+                                         int64_t e0, const Op &op, double gamma, double *lds, double *sref,
+                                         const Work &work = Work{}, const double *__restrict__ aux = nullptr) {
+    using G = Geom<N, DIM>;
+    using L = SfLayout<N, DIM, P>;
+    using R = typename P::Real;
+    constexpr int AS = L::AS;
+    constexpr int NREF = L::NREF;
+    R *lin = reinterpret_cast<R *>(lds);  // staged inputs: NS arrays of type R
+    double *lout = lds;                   // outputs: NV arrays of doubles
+
+    const int tid = threadIdx.x;
+    const int nel = (int)((E - e0) < G::EPB ? (E - e0) : G::EPB);
+    const int nvalid = nel * G::NODES;
+    const size_t vstride = (size_t)E * G::NODES;
+    const size_t gbase = (size_t)e0 * G::NODES;
+
+    // a1: per-element reference values (from each element's first node), then
+    // stage the block's nodes.
+    if (P::NREF > 0) {
+        if (tid < nel) {
+            double uc[P::NV];
+#pragma unroll
+            for (int v = 0; v < P::NV; ++v) uc[v] = u[v * vstride + gbase + (size_t)tid * G::NODES];
+            P::make_ref(uc, gamma, sref + tid * NREF);
+        }
+        __syncthreads();
+    }
+    // every load of the staging pass is issued before any conversion
+    constexpr int SPT = (G::EPB * G::NODES + G::THREADS - 1) / G::THREADS;  // nodes per thread
+    double uc[SPT][P::NV + P::NX];  // conserved variables, then P::NX extra inputs from aux
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        const int i = tid + k * G::THREADS;
+        if (i < nvalid) {
+#pragma unroll
+            for (int v = 0; v < P::NV; ++v) uc[k][v] = u[v * vstride + gbase + i];
+#pragma unroll
+            for (int x = 0; x < P::NX; ++x) uc[k][P::NV + x] = aux[x * vstride + gbase + i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        const int i = tid + k * G::THREADS;
+        if (i < nvalid) {
+            R s[P::NS];
+            P::stage(uc[k], sref + (i / G::NODES) * NREF, gamma, s);
+            const int el = i / G::NODES, node = i - el * G::NODES;
+            const int li = el * G::PADN + G::pidx(node);
+#pragma unroll
+            for (int q = 0; q < P::NS; ++q) lin[q * AS + li] = s[q];
+        }
+    }
+    __syncthreads();
+
+    // a2..a5: one line per lane.
+    const int m = tid / G::LPD;
+    const int r = tid - m * G::LPD;
+    const int el = r / G::LINES;
+    const int line = r - el * G::LINES;
+    const bool active = el < nel;
+    int pbase, pstride, q0, q1;
+    line_geometry<N, DIM>(m, line, pbase, pstride, q0, q1);
+    const double wperp = DIM == 3 ? op.w(q0) * op.w(q1) : op.w(q0);
+    const typename P::Consts K = P::consts(0.5 / (gamma - 1.0));
+    const R *le = lin + el * G::PADN;
+
+    R t[N][P::NV];
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+        for (int k = 0; k < P::NV; ++k) t[a][k] = (R)0;
+
+    if (active) {
+        // m is uniform per wave; one instantiation per direction turns the
+        // rotated array offsets into immediates
+        const int64_t e = e0 + el;
+        const double *ref = sref + el * NREF;
+        if (m == 0)
+            work.template lines<0, N, P>(le, AS, pbase, pstride, op, K, gamma, t, e, line, wperp, ref);
+        else if (DIM == 2 || m == 1)
+            work.template lines<1, N, P>(le, AS, pbase, pstride, op, K, gamma, t, e, line, wperp, ref);
+        else
+            work.template lines<2, N, P>(le, AS, pbase, pstride, op, K, gamma, t, e, line, wperp, ref);
+    }
+    __syncthreads();  // every lane is done reading the staged inputs
+
+    // a6: FP64 direction sum in the fixed order m = 0, 1, ..., d-1 (bit
+    // reproducible): the first directions accumulate in LDS (the output
+    // arrays reuse the input space), the last adds its own sums to the LDS
+    // total and stores the result (for fixed a, the lanes of the last
+    // direction cover consecutive nodes: coalesced).
+    double *lo = lout + el * G::PADN;
+    const size_t obase = gbase + (size_t)el * G::NODES;
+#pragma unroll
+    for (int mm = 0; mm < DIM; ++mm) {
+        if (m == mm && active) {
+            const int nstride = DIM == 3 ? N * N : N;  // node stride of the last direction
+            const int nbase = DIM == 3 ? q0 + N * q1 : q0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                const int idx = pbase + a * pstride;
+#pragma unroll
+                for (int k = 0; k < P::NV; ++k) {
+                    double *dst = lo + P::out_array(k, m) * AS + idx;
+                    const double val = (double)t[a][k] * wperp;
+                    if (mm == 0)
+                        *dst = val;
+                    else if (mm < DIM - 1)
+                        *dst = *dst + val;
+                    else
+                        out[P::out_array(k, m) * vstride + obase + nbase + a * nstride] = *dst + val;
+                }
+            }
+        }
+        if (mm < DIM - 1) __syncthreads();
+    }
+}
+
+}  // namespace dev
+}  // namespace sfhad

@@ -53,7 +53,7 @@ struct VolumeRequest {
 };
 enum { kModeVolume = 0, kModeSurface = 1, kModeVolumeSurface = 2 };
 
-// Kernel launchers (volume_kernels.hip / dense_kernels.hip).  They return
+// Kernel launchers (volume_kernels.hip, surface_kernels.hip, dense_kernels.hip).  They return
 // SF_OK, SF_ERR_UNSUPPORTED for a shape that is not instantiated, or
 // SF_ERR_HIP when the launch fails.
 int launch_sf_volume(const VolumeRequest &r);
