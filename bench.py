@@ -332,8 +332,16 @@ def main() -> int:
                 step32()
             t32, k32 = timed_launches(torch, step32, args.steps, stream)
             ms32 = t32 / args.steps
+            # the same pair / diagonal operation model against the unpacked
+            # FP32 issue rate (one lane-operation per lane per cycle, as for
+            # FP64: packed FP32 is not used), and the HBM fraction
+            ops32 = model_ops_per_element(n) * w.E / (k32 * 1e-3)
+            bytes32 = 2 * 5 * n ** 3 * 8 * w.E
             result["fp32_split"] = {"value": dof / (ms32 * 1e-3), "unit": "DOF/s", "ms_per_step": ms32,
-                                    "kernel_ms": k32, "speedup_vs_fp64": ms_per_step / ms32}
+                                    "kernel_ms": k32, "speedup_vs_fp64": ms_per_step / ms32,
+                                    "model_issue_frac": round(ops32 / PEAK_FP64_LANE_OPS, 4),
+                                    "hbm_algorithmic_GBps": round(bytes32 / (k32 * 1e-3) / 1e9, 1),
+                                    "hbm_frac": round(bytes32 / (k32 * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
             log(f"[bench] FP32-split: {ms32:.4f} ms/step ({ms_per_step / ms32:.2f}x FP64)")
 
         if want("dense"):

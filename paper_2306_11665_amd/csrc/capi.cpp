@@ -58,7 +58,10 @@ int validate(const double *u, int64_t E, int n, int d, int flux, double *out, co
         if (o.precision != SF_PREC_FP64) return fail(SF_ERR_UNSUPPORTED, "dense path is FP64 only");
     }
     const int64_t N = ipow(n, d);
-    if (E > 0 && E > INT64_MAX / (N * nv)) return fail(SF_ERR_ARG, "elem_count too large");
+    // every byte count derived from E below (state, facet and metric arrays:
+    // at most 16 doubles per node and element) must fit in int64
+    if (E > 0 && E > INT64_MAX / (N * 16 * (int64_t)sizeof(double)))
+        return fail(SF_ERR_ARG, "elem_count too large");
     r.E = E;
     r.n = n;
     r.d = d;

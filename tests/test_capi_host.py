@@ -92,6 +92,11 @@ def test_validation_errors(sf, fn):
     assert f(BAD, 4, 4, 3, 1, BAD) == -1                  # out aliases u
     assert f(BAD, 4, 4, 3, 1, BAD + 100) == -1            # out overlaps u
     assert f(None, 0, 4, 3, 1, None) == 0                 # E = 0: no-op
+    # element counts whose byte counts (up to 16 doubles per node) leave int64
+    emax = (2 ** 63 - 1) // (64 * 16 * 8)
+    assert f(BAD, emax + 1, 4, 3, 1, BAD + 10 ** 9) == -1
+    assert "too large" in sf.last_error()
+    assert f(BAD, 2 ** 62, 16, 3, 0, BAD + 10 ** 9) == -1
 
 
 def test_opts_validation(sf):
