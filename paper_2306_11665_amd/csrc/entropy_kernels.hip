@@ -13,14 +13,17 @@
 // One workgroup per element: the nodal entropy variables go to LDS (one
 // padded array per component), then each thread takes facet nodes in the
 // output order (face-major, t fastest: coalesced stores) and interpolates
-// along its line.  HBM-bound: 8 B x 5 x (n^3 + 6 n^2) per element.
+// along its line.  Moves 8 B x 5 x (n^3 + 6 n^2) per element; the logarithms
+// and exponentials (ocml, full FP64 accuracy) make it about as much VALU- as
+// HBM-bound.  Quotients are products with a refined reciprocal (about one
+// ulp), the 1/(gamma - 1) factors one reciprocal per thread.
 #include "kernels_common.h"
 #include "sfhad_internal.h"
 
 namespace sfhad {
 namespace dev {
 
-constexpr int kTraceThreads = 256;
+constexpr int kTraceThreads = 128;  // n = 8: 512 nodes and 384 facet nodes, no idle lane
 
 template <int N>
 struct TraceArgs {
@@ -47,18 +50,19 @@ __global__ void __launch_bounds__(kTraceThreads) entropy_trace_kernel(const Trac
     const int tid = threadIdx.x;
     const int64_t e = blockIdx.x;
     const double g = A->gamma;
+    const double igm1 = uniform_f64(1.0 / (g - 1.0));
     const size_t vs = (size_t)A->E * NODES, base = (size_t)e * NODES;
     for (int i = tid; i < NODES; i += kTraceThreads) {
         const double rho = A->u[base + i];
-        const double irho = 1.0 / rho;
+        const double irho = rcp_fine(rho);
         const double vx = A->u[vs + base + i] * irho, vy = A->u[2 * vs + base + i] * irho,
                      vz = A->u[3 * vs + base + i] * irho;
         const double q = vx * vx + vy * vy + vz * vz;
         const double p = (g - 1.0) * (A->u[4 * vs + base + i] - 0.5 * rho * q);
-        const double rp = rho / p;
+        const double rp = rho * rcp_fine(p);
         const double s = log(p) - g * log(rho);
         const int li = i + i / N;
-        sv[li] = (g - s) / (g - 1.0) - 0.5 * rp * q;
+        sv[li] = (g - s) * igm1 - 0.5 * rp * q;
         sv[PAD + li] = rp * vx;
         sv[2 * PAD + li] = rp * vy;
         sv[3 * PAD + li] = rp * vz;
@@ -80,16 +84,17 @@ __global__ void __launch_bounds__(kTraceThreads) entropy_trace_kernel(const Trac
             for (int c = 0; c < 5; ++c) v[c] = __builtin_fma(l, sv[c * PAD + li], v[c]);
         }
         const double rp = -v[4];
-        const double vx = v[1] / rp, vy = v[2] / rp, vz = v[3] / rp;
+        const double irp = rcp_fine(rp);
+        const double vx = v[1] * irp, vy = v[2] * irp, vz = v[3] * irp;
         const double q = vx * vx + vy * vy + vz * vz;
         const double s = g - (g - 1.0) * (v[0] + 0.5 * rp * q);
-        const double rho = exp((s + log(rp)) / (1.0 - g));
-        const double p = rho / rp;
+        const double rho = exp(-(s + log(rp)) * igm1);
+        const double p = rho * irp;
         A->uf[fbase + j] = rho;
         A->uf[fs + fbase + j] = rho * vx;
         A->uf[2 * fs + fbase + j] = rho * vy;
         A->uf[3 * fs + fbase + j] = rho * vz;
-        A->uf[4 * fs + fbase + j] = p / (g - 1.0) + 0.5 * rho * q;
+        A->uf[4 * fs + fbase + j] = p * igm1 + 0.5 * rho * q;
     }
 }
 
@@ -123,35 +128,37 @@ int launch_trace(const double *u, double *uf, int64_t E, double gamma, const Ope
 // basis transformation (u(V P v(u)) on any node set).
 __global__ void __launch_bounds__(256) entropy_map_kernel(const double *__restrict__ in, double *__restrict__ out,
                                                          int64_t count, double g, int dir) {
+    const double igm1 = 1.0 / (g - 1.0);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double x0 = in[i], x1 = in[count + i], x2 = in[2 * count + i], x3 = in[3 * count + i],
                      x4 = in[4 * count + i];
         double y0, y1, y2, y3, y4;
         if (dir == 0) {
-            const double irho = 1.0 / x0;
+            const double irho = rcp_fine(x0);
             const double vx = x1 * irho, vy = x2 * irho, vz = x3 * irho;
             const double q = vx * vx + vy * vy + vz * vz;
             const double p = (g - 1.0) * (x4 - 0.5 * x0 * q);
-            const double rp = x0 / p;
+            const double rp = x0 * rcp_fine(p);
             const double s = log(p) - g * log(x0);
-            y0 = (g - s) / (g - 1.0) - 0.5 * rp * q;
+            y0 = (g - s) * igm1 - 0.5 * rp * q;
             y1 = rp * vx;
             y2 = rp * vy;
             y3 = rp * vz;
             y4 = -rp;
         } else {
             const double rp = -x4;
-            const double vx = x1 / rp, vy = x2 / rp, vz = x3 / rp;
+            const double irp = rcp_fine(rp);
+            const double vx = x1 * irp, vy = x2 * irp, vz = x3 * irp;
             const double q = vx * vx + vy * vy + vz * vz;
             const double s = g - (g - 1.0) * (x0 + 0.5 * rp * q);
-            const double rho = exp((s + log(rp)) / (1.0 - g));
-            const double p = rho / rp;
+            const double rho = exp(-(s + log(rp)) * igm1);
+            const double p = rho * irp;
             y0 = rho;
             y1 = rho * vx;
             y2 = rho * vy;
             y3 = rho * vz;
-            y4 = p / (g - 1.0) + 0.5 * rho * q;
+            y4 = p * igm1 + 0.5 * rho * q;
         }
         out[i] = y0;
         out[count + i] = y1;
