@@ -207,7 +207,7 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per offered load")
     ap.add_argument("--legs", default="all",
-                    help="comma list of extra legs (fp32, dense, tensor, surface, curvilinear, entropy, graph, "
+                    help="comma list of extra legs (fp32, dense, tensor, surface, curvilinear, entropy, uncollocated, graph, "
                          "figure1, serving) or 'all'")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain device-to-device copy of the input's size (counter calibration)")
@@ -466,6 +466,50 @@ def main() -> int:
                 "hbm_frac": round(ebytes / (ke * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
             log(f"[bench] entropy trace: {ke * 1e3:.1f} us/launch, {ebytes / (ke * 1e-3) / 1e9:.0f} GB/s")
             del ufe
+
+        if want("uncollocated"):
+            # the uncollocated modal path (the proof of Theorem 1): n = 8 modes,
+            # m = 10 GL quadrature nodes per direction; modal state u_hat ->
+            # u_q = V u_hat -> entropy projection u(V P v(u_q)) -> volume term
+            # on the m-node set -> V^T y back to the modes.  Smooth (linear
+            # primitive) fields keep every interpolated state physical.
+            m = n + 2
+            us = torch.from_numpy(W.smooth_euler_state(E, n, seed=11)).cuda()
+            _, Pn = sfhad.basis_rect(n, n, "gl")
+            Vm, Pm = sfhad.basis_rect(n, m, "gl")
+            VmT = np.ascontiguousarray(Vm.T)
+            uh = sfhad.tensor_apply(us, n, 3, Pn, stream=stream)
+            del us
+            bq0 = torch.empty((5, E, m ** 3), dtype=torch.float64, device="cuda")
+            bq1 = torch.empty_like(bq0)
+            vh = torch.empty_like(uh)
+            rh = torch.empty_like(uh)
+
+            def stepu():
+                sfhad.tensor_apply(uh, n, 3, Vm, out=bq0, stream=stream)        # u_q
+                sfhad.entropy_variables(bq0, out=bq1, stream=stream)            # v(u_q)
+                sfhad.tensor_apply(bq1, m, 3, Pm, out=vh, stream=stream)        # P v
+                sfhad.tensor_apply(vh, n, 3, Vm, out=bq0, stream=stream)        # V P v
+                sfhad.conserved_variables(bq0, out=bq0, stream=stream)          # u~_q
+                sfhad.volume(bq0, m, 3, "euler", out=bq1, stream=stream)        # y_q
+                sfhad.tensor_apply(bq1, m, 3, VmT, out=rh, stream=stream)       # V^T y_q
+
+            def stepv():
+                sfhad.volume(bq0, m, 3, "euler", out=bq1, stream=stream)
+
+            for _ in range(args.warmup):
+                stepu()
+            _, ku = timed_launches(torch, stepu, args.steps, stream)
+            _, kv = timed_launches(torch, stepv, args.steps, stream)
+            ok = bool(torch.isfinite(rh).all().item())
+            result["uncollocated"] = {
+                "what": "modal path, n = 8 modes on m = 10 GL quadrature nodes, 32768 elements: "
+                        "interpolation, entropy projection, volume term on the m-node set, V^T back to the modes",
+                "ms_per_residual": ku, "volume_ms_m10": kv, "volume_share": round(kv / ku, 3),
+                "elem_evals_per_s": E / (ku * 1e-3), "finite": ok}
+            log(f"[bench] uncollocated n=8 -> m=10: {ku * 1e3:.1f} us per residual "
+                f"(volume term on the 10^3 nodes {kv * 1e3:.1f} us)")
+            del bq0, bq1, vh, rh, uh
 
         if want("graph"):
             # n = 4 workload: 100 launches captured in one HIP graph

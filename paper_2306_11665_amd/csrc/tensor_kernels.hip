@@ -199,19 +199,36 @@ int dispatch_tensor(const TensorRequest &r) {
 // extents (directions before m already n_out); each stage is stored with x
 // fastest and one pad slot per x-row.  Same MFMA scheme and in-place single
 // buffer as the square kernel; the A operand rows q < n_out, k < n_in.
+//
+// Every index split divides by a run-time size (n_in, n_out, n_in^d, the
+// lines per slab of a pass).  Instead of integer division (a long
+// instruction sequence) the kernel multiplies by a reciprocal from the host:
+// floor(x / d) = mulhi(x, ceil(2^32 / d)) exactly when x e < 2^32,
+// e = ceil(2^32 / d) d - 2^32 < d (write x = q d + r: the product is
+// q + r/d + x e / (d 2^32), below q + 1 when r <= d - 1 and x e < 2^32).
+// Here d <= 4352 and x <= 4352 (an index inside the block's LDS stage or
+// its lines), so x e < 2^25.
+constexpr int kRectTPW = 8;       // 16-line tiles per wave and pass (at most)
+constexpr int kRectStage = 4096;  // LDS doubles per block for the slabs (plus pads)
+
 struct RectArgs {
     const double *in;
     double *out;
     int64_t slabs;
     int ni, no, G, cap;  // sizes, slabs per block, LDS doubles per slab
+    uint32_t rc_ni, rc_no, rc_nin;  // ceil(2^32 / d) of n_in, n_out, n_in^d
+    uint32_t rc_lps[3];             // of the lines per slab of pass m
     double M[kMaxN * kMaxN];  // row-major n_out x n_in (row stride n_in)
 };
+
+__device__ __forceinline__ int qdiv(int x, uint32_t rc) { return (int)__umulhi((uint32_t)x, rc); }
 
 template <int DIM>
 __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectArgs) {
     extern __shared__ double buf[];
     const auto A = kernel_args<RectArgs>();
     const int ni = A->ni, no = A->no, G = A->G, cap = A->cap;
+    const uint32_t rc_ni = A->rc_ni, rc_no = A->rc_no;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int nin = 1, nout = 1;
 #pragma unroll
@@ -222,10 +239,23 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
     const int64_t s0 = (int64_t)blockIdx.x * G;
     const int gs = (int)((A->slabs - s0) < G ? (A->slabs - s0) : G);
     const double *src = A->in + s0 * nin;
-    // stage 0: the input slabs, x fastest, one pad per x-row of n_in
-    for (int i = tid; i < gs * nin; i += kTensorThreads) {
-        const int g = i / nin, lin = i - g * nin;
-        buf[g * cap + lin + lin / ni] = src[i];
+    // stage 0: the input slabs, x fastest, one pad per x-row of n_in; every
+    // load is issued before the first LDS store
+    constexpr int SPT = kRectStage / kTensorThreads;
+    const int total = gs * nin;
+    double v[SPT];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int i = tid + j * kTensorThreads;
+        if (i < total) v[j] = src[i];
+    }
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int i = tid + j * kTensorThreads;
+        if (i < total) {
+            const int g = qdiv(i, A->rc_nin), lin = i - g * nin;
+            buf[g * cap + lin + qdiv(lin, rc_ni)] = v[j];
+        }
     }
     const int q_a = lane & 15, kq = lane >> 4;
     double a[4];
@@ -240,10 +270,12 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
     for (int m = 0; m < DIM; ++m) {
         // extents at stage m (before the pass) and stage m + 1 (after)
         int ext[3], exo[3];
+        uint32_t rce[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             ext[k] = k < DIM ? (k < m ? no : ni) : 1;
             exo[k] = k < DIM ? (k <= m ? no : ni) : 1;
+            rce[k] = k < m ? rc_no : rc_ni;  // used for k < DIM, k != m only
         }
         int lps = 1;  // lines per slab
 #pragma unroll
@@ -251,58 +283,66 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
             if (k != m) lps *= ext[k];
         const int nlines = gs * lps;
         const int tiles = (nlines + 15) >> 4;
-        d4 acc[4];
-        int cz[4][3];
-        int gg[4];
-        bool ok[4];
+        // Padded stage index of coordinates c (x fastest, one pad per x-row):
+        // c0 + ext0 R + floor((c0 + ext0 R) / ext0) = c0 + (ext0 + 1) R with
+        // R = c1 + ext1 c2, so a line of direction m is base + k * stride.
+        const int si1 = ext[0] + 1, si2 = (ext[0] + 1) * ext[1];
+        const int so1 = exo[0] + 1, so2 = (exo[0] + 1) * exo[1];
+        const int sg1 = exo[0], sg2 = exo[0] * exo[1];  // unpadded (the output array)
+        const int str_in = m == 0 ? 1 : (m == 1 ? si1 : si2);
+        const int str_out = m == 0 ? 1 : (m == 1 ? so1 : so2);
+        const int str_g = m == 0 ? 1 : (m == 1 ? sg1 : sg2);
+        d4 acc[kRectTPW];
+        int bout[kRectTPW];  // output base: LDS index, or the element offset in `out`
+        bool ok[kRectTPW];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kRectTPW; ++u) {
             const int t = wave + 4 * u;  // wave-uniform
             acc[u] = d4{0.0, 0.0, 0.0, 0.0};
             ok[u] = false;
+            bout[u] = 0;
             if (t >= tiles) continue;
             const int Lg = t * 16 + (lane & 15);
             ok[u] = Lg < nlines;
-            const int g = ok[u] ? Lg / lps : 0;
+            const int g = ok[u] ? qdiv(Lg, A->rc_lps[m]) : 0;
             int L = ok[u] ? Lg - g * lps : 0;
-            gg[u] = g;
             // coordinates of the other directions, increasing order, first fastest
+            int c[3] = {0, 0, 0};
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                if (k == m || k >= DIM) {
-                    cz[u][k] = 0;
-                    continue;
-                }
-                cz[u][k] = L % ext[k];
-                L /= ext[k];
+            for (int k = 0; k < DIM; ++k) {
+                if (k == m) continue;
+                const int qk = qdiv(L, rce[k]);
+                c[k] = L - qk * ext[k];
+                L = qk;
             }
-            for (int s = 0; s < ks; ++s) {
+            const int bin = g * cap + c[0] + si1 * c[1] + si2 * c[2];
+            bout[u] = m == DIM - 1 ? g * nout + c[0] + sg1 * c[1] + sg2 * c[2]
+                                   : g * cap + c[0] + so1 * c[1] + so2 * c[2];
+            // the tile's B operands first (up to 4 LDS reads in flight), then
+            // the MFMAs; ks is wave-uniform
+            double b[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
                 const int k = 4 * s + kq;
-                double b = 0.0;
-                if (ok[u] && k < ni) {
-                    int c[3] = {cz[u][0], cz[u][1], cz[u][2]};
-                    c[m] = k;
-                    const int lin = c[0] + ext[0] * (c[1] + ext[1] * c[2]);
-                    b = buf[g * cap + lin + lin / ext[0]];
-                }
-                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b, acc[u], 0, 0, 0);
+                b[s] = (s < ks && ok[u] && k < ni) ? buf[bin + k * str_in] : 0.0;
             }
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                if (s < ks) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc[u], 0, 0, 0);
         }
         if (m < DIM - 1) __syncthreads();  // every read of this pass is done
+        double *dst = A->out + s0 * nout;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kRectTPW; ++u) {
             if (!ok[u]) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int q = 4 * r + kq;
                 if (q >= no) continue;
-                int c[3] = {cz[u][0], cz[u][1], cz[u][2]};
-                c[m] = q;
-                const int lin = c[0] + exo[0] * (c[1] + exo[1] * c[2]);
                 if (m == DIM - 1)
-                    A->out[(s0 + gg[u]) * nout + lin] = acc[u][r];
+                    dst[bout[u] + q * str_g] = acc[u][r];
                 else
-                    buf[gg[u] * cap + lin + lin / exo[0]] = acc[u][r];
+                    buf[bout[u] + q * str_out] = acc[u][r];
             }
         }
         if (m < DIM - 1) __syncthreads();
@@ -325,8 +365,10 @@ int launch_tensor_rect(const TensorRequest &r) {
     int mxd = 1, mxl = 1;
     for (int k = 0; k < r.d; ++k) mxd *= mx;
     mxl = mxd / mx;
-    int G = 2048 / mxd;
-    if (256 / mxl < G) G = 256 / mxl;
+    // slabs per block: the LDS stage holds kRectStage doubles, and the
+    // lines of a pass fill at most 4 waves x kRectTPW tiles of 16
+    int G = kRectStage / mxd;
+    if (64 * kRectTPW / mxl < G) G = 64 * kRectTPW / mxl;
     if (G < 1) G = 1;
     RectArgs a;
     a.in = r.in;
@@ -336,6 +378,18 @@ int launch_tensor_rect(const TensorRequest &r) {
     a.no = r.n_out;
     a.G = G;
     a.cap = mxd + mxl;
+    auto rc = [](int64_t d) { return (uint32_t)(((int64_t)1 << 32) / d + ((((int64_t)1 << 32) % d) != 0)); };
+    int nin = 1;
+    for (int k = 0; k < r.d; ++k) nin *= r.n;
+    a.rc_ni = rc(r.n);
+    a.rc_no = rc(r.n_out);
+    a.rc_nin = rc(nin);
+    for (int m = 0; m < 3; ++m) {
+        int lps = 1;
+        for (int k = 0; k < r.d; ++k)
+            if (k != m) lps *= k < m ? r.n_out : r.n;
+        a.rc_lps[m] = m < r.d ? rc(lps) : 0;
+    }
     for (int i = 0; i < r.n_out * r.n; ++i) a.M[i] = r.M[i];
     const int64_t blocks = (a.slabs + G - 1) / G;
     if (blocks > 0x7fffffffLL) {

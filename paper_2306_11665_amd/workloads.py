@@ -151,6 +151,23 @@ def reference_nodes(n: int, nodes: str = "gl") -> np.ndarray:
     return np.concatenate([[-1.0], np.sort(interior.real), [1.0]])
 
 
+def smooth_euler_state(E: int, n: int, seed: int, nodes: str = "gl", slope: float = 0.15) -> np.ndarray:
+    """Conserved state (5, E, n^3) of primitive fields that are linear in each
+    element (rho, p = 1 + g . x, |g_k| <= slope; vel_k = c_k + g . x), so the
+    polynomial interpolant of the state stays physical on any node set of the
+    element (inputs of the over-integrated and entropy-projected paths)."""
+    x = reference_nodes(n, nodes)
+    node = np.arange(n ** 3)
+    X = np.stack([x[node % n], x[(node // n) % n], x[node // (n * n)]])   # (3, n^3)
+    rng = np.random.default_rng(seed)
+    g = rng.uniform(-slope, slope, (5, E, 3))
+    c = rng.uniform(-0.3, 0.3, (3, E))
+    rho = 1.0 + g[0] @ X
+    p = 1.0 + g[1] @ X
+    vel = np.stack([c[k][:, None] + g[2 + k] @ X for k in range(3)])
+    return np.ascontiguousarray(primitives_to_conserved(rho, vel, p))
+
+
 def warped_mesh_metrics(E: int, n: int, nodes: str = "gl", amp: float = 0.02, length: float = 2 * math.pi):
     """Contravariant metric terms Ja^m_k = J d xi^m / d x_k, shape (3, 3, E, n^3)
     ([m][k][e][node], node = ix + n iy + n^2 iz), of a non-symmetrically

@@ -143,7 +143,7 @@ def test_rectangular_every_shape_class(torch_dev, sf, orc, ni, no, d):
     M = rng.normal(size=(no, ni))
     nvar = 5
     mx = max(ni, no)
-    G = max(1, min(2048 // mx ** d, 256 // mx ** (d - 1)))
+    G = max(1, min(4096 // mx ** d, 512 // mx ** (d - 1)))
     slabs = 3 * G + 1
     E = -(-slabs // nvar)
     u = rng.normal(size=(nvar, E, ni ** d))
