@@ -161,6 +161,20 @@ def _check_tensor(u, flux: str, n: int, d: int):
         raise ValueError(f"u must be a contiguous ({nv}, E, {n ** d}) tensor, got {tuple(u.shape)}")
 
 
+def _check_out(out, shape, like, what: str = "out"):
+    """A caller-provided output: a contiguous float64 tensor of `shape` on the
+    device of `like` (a host tensor's pointer would reach the kernel)."""
+    import torch
+    if (not isinstance(out, torch.Tensor) or out.device != like.device or out.dtype != torch.float64
+            or not out.is_contiguous() or tuple(out.shape) != tuple(shape)):
+        raise ValueError(f"{what} must be a contiguous float64 tensor {tuple(shape)} on {like.device}")
+
+
+def _check_same_device(x, like, what: str):
+    if x.device != like.device:
+        raise ValueError(f"{what} must be on {like.device}, got {x.device}")
+
+
 def _call(fn_name: str, u, n: int, d: int, flux: str, *, nodes="gl", precision="fp64", gamma=1.4,
           stream=None, out=None, Q=None, w=None):
     import torch
@@ -168,7 +182,7 @@ def _call(fn_name: str, u, n: int, d: int, flux: str, *, nodes="gl", precision="
     if out is None:
         out = torch.empty_like(u)
     else:
-        _check_tensor(out, flux, n, d)
+        _check_out(out, u.shape, u)
     opts, keep = make_opts(nodes, precision, gamma, stream, Q, w)
     fn = getattr(lib(), fn_name)
     check(fn(u.data_ptr(), u.shape[1], n, d, FLUX[flux], out.data_ptr(), ctypes.byref(opts)), fn_name)
@@ -195,7 +209,11 @@ def volume_curvilinear(u, Ja, n: int, flux: str = "euler", *, nodes="gl", gamma=
     if (not isinstance(Ja, torch.Tensor) or Ja.device.type != "cuda" or Ja.dtype != torch.float64
             or not Ja.is_contiguous() or tuple(Ja.shape) != (3, 3, E, n ** 3)):
         raise ValueError(f"Ja must be a contiguous float64 CUDA tensor (3, 3, {E}, {n ** 3})")
-    out = torch.empty_like(u) if out is None else out
+    _check_same_device(Ja, u, "Ja")
+    if out is None:
+        out = torch.empty_like(u)
+    else:
+        _check_out(out, u.shape, u)
     opts, keep = make_opts(nodes, "fp64", gamma, stream)
     check(lib().sf_hadamard_volume_curvilinear(u.data_ptr(), Ja.data_ptr(), E, n, FLUX[flux], out.data_ptr(),
                                                ctypes.byref(opts)), "sf_hadamard_volume_curvilinear")
@@ -208,9 +226,10 @@ def _entropy_map(name, x, gamma, stream, out):
     if not isinstance(x, torch.Tensor) or x.device.type != "cuda" or x.dtype != torch.float64 \
             or not x.is_contiguous() or x.shape[0] != 5:
         raise ValueError("expected a contiguous float64 CUDA tensor with 5 leading components")
-    out = torch.empty_like(x) if out is None else out
-    if out.shape != x.shape or not out.is_contiguous() or out.dtype != x.dtype:
-        raise ValueError("out must match the input")
+    if out is None:
+        out = torch.empty_like(x)
+    else:
+        _check_out(out, x.shape, x)
     check(getattr(lib(), name)(x.data_ptr(), x.numel() // 5, out.data_ptr(), float(gamma), _stream_handle(stream)),
           name)
     return out
@@ -232,9 +251,10 @@ def entropy_trace(u, n: int, *, nodes="gl", gamma=1.4, stream=None, out=None):
     import torch
     _check_tensor(u, "euler", n, 3)
     E = u.shape[1]
-    out = torch.empty((5, E, 6, n * n), dtype=u.dtype, device=u.device) if out is None else out
-    if tuple(out.shape) != (5, E, 6, n * n) or not out.is_contiguous() or out.dtype != u.dtype:
-        raise ValueError("out must be a contiguous (5, E, 6, n^2) float64 tensor")
+    if out is None:
+        out = torch.empty((5, E, 6, n * n), dtype=u.dtype, device=u.device)
+    else:
+        _check_out(out, (5, E, 6, n * n), u)
     opts, keep = make_opts(nodes, "fp64", gamma, stream)
     check(lib().sf_entropy_trace(u.data_ptr(), E, n, out.data_ptr(), ctypes.byref(opts)), "sf_entropy_trace")
     del keep
@@ -261,8 +281,15 @@ def surface(u, uf, n: int, d: int, flux: str, *, with_volume=False, nodes="gl", 
     if (not isinstance(uf, torch.Tensor) or uf.device.type != "cuda" or uf.dtype != torch.float64
             or not uf.is_contiguous() or tuple(uf.shape) != (nv, E, 2 * d, n ** (d - 1))):
         raise ValueError(f"u_face must be a contiguous float64 CUDA tensor ({nv}, {E}, {2 * d}, {n ** (d - 1)})")
-    y_vol = torch.empty_like(u) if y_vol is None else y_vol
-    y_face = torch.empty_like(uf) if y_face is None else y_face
+    _check_same_device(uf, u, "u_face")
+    if y_vol is None:
+        y_vol = torch.empty_like(u)
+    else:
+        _check_out(y_vol, u.shape, u, "y_vol")
+    if y_face is None:
+        y_face = torch.empty_like(uf)
+    else:
+        _check_out(y_face, uf.shape, u, "y_face")
     opts, keep = make_opts(nodes, "fp64", gamma, stream, None if w is None else np.zeros((n, n)), w)
     name = "sf_hadamard_volume_surface" if with_volume else "sf_hadamard_surface"
     check(getattr(lib(), name)(u.data_ptr(), uf.data_ptr(), E, n, d, FLUX[flux], y_vol.data_ptr(),

@@ -377,3 +377,39 @@ def test_concurrent_host_threads_on_own_streams(torch_dev, sf):
         torch.cuda.synchronize()
         for r in outs[i]:
             assert torch.equal(r, ref), (n, kind)
+
+
+def test_binding_rejects_outputs_off_the_device(torch_dev, sf):
+    """Caller-provided outputs must be contiguous float64 tensors on the input's
+    device: a host tensor is refused before any launch (its pointer would
+    reach the kernel)."""
+    torch = torch_dev
+    from paper_2306_11665_amd import workloads as W
+    n, E = 3, 4
+    u_np = W.euler_state(E, n, seed=1)
+    u = torch.from_numpy(u_np).cuda()
+    # facet states: each element's first node state on all of its facet nodes
+    uf = torch.from_numpy(np.ascontiguousarray(
+        np.repeat(u_np[:, :, :1], 6 * n * n, axis=2).reshape(5, E, 6, n * n))).cuda()
+    host = torch.empty((5, E, n ** 3), dtype=torch.float64)
+    with pytest.raises(ValueError):
+        sf.volume(u, n, 3, "euler", out=host)
+    with pytest.raises(ValueError):
+        sf.volume(u, n, 3, "euler", out=torch.empty((5, E, n ** 3), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        sf.entropy_variables(u, out=host)
+    with pytest.raises(ValueError):
+        sf.entropy_trace(u, n, out=torch.empty((5, E, 6, n * n), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        sf.surface(u, uf, n, 3, "euler", y_vol=host)
+    with pytest.raises(ValueError):
+        sf.surface(u, uf, n, 3, "euler", y_face=torch.empty((5, E, 6, n * n), dtype=torch.float64))
+    Ja = torch.zeros((3, 3, E, n ** 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        sf.volume_curvilinear(u, Ja, n, out=host)
+    with pytest.raises(ValueError):
+        sf.tensor_apply(u, n, 3, np.eye(n), out=host)
+    # the same calls with device outputs run
+    y = sf.volume(u, n, 3, "euler", out=torch.empty_like(u))
+    torch.cuda.synchronize()
+    assert torch.isfinite(y).all()
