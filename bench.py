@@ -277,6 +277,8 @@ def main() -> int:
         roofline["traffic"] = int(round(ctr["fetch_kib"] * 1024 * ctr["fetch_scale"]
                                         + ctr["write_kib"] * 1024 * ctr["write_scale"]))
         roofline["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
+        roofline["hbm_measured_GBps"] = round(roofline["traffic"] / (kern_ms * 1e-3) / 1e9, 1)
+        roofline["hbm_measured_frac"] = round(roofline["traffic"] / (kern_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
         if "f64_wave_insts" in ctr:
             roofline["measured_f64_lane_ops_per_element"] = round(ctr["f64_wave_insts"] * 64 / E, 1)
             roofline["measured_valu_f64_issue_util"] = ctr.get("valu_f64_util")
