@@ -222,6 +222,8 @@ struct RectArgs {
 };
 
 __device__ __forceinline__ int qdiv(int x, uint32_t rc) { return (int)__umulhi((uint32_t)x, rc); }
+// index products: every factor is below 2^16, so the full-rate 24-bit multiply is exact
+__device__ __forceinline__ int m24(int a, int b) { return __mul24(a, b); }
 
 template <int DIM>
 __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectArgs) {
@@ -253,8 +255,8 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
     for (int j = 0; j < SPT; ++j) {
         const int i = tid + j * kTensorThreads;
         if (i < total) {
-            const int g = qdiv(i, A->rc_nin), lin = i - g * nin;
-            buf[g * cap + lin + qdiv(lin, rc_ni)] = v[j];
+            const int g = qdiv(i, A->rc_nin), lin = i - m24(g, nin);
+            buf[m24(g, cap) + lin + qdiv(lin, rc_ni)] = v[j];
         }
     }
     const int q_a = lane & 15, kq = lane >> 4;
@@ -305,26 +307,26 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
             const int Lg = t * 16 + (lane & 15);
             ok[u] = Lg < nlines;
             const int g = ok[u] ? qdiv(Lg, A->rc_lps[m]) : 0;
-            int L = ok[u] ? Lg - g * lps : 0;
+            int L = ok[u] ? Lg - m24(g, lps) : 0;
             // coordinates of the other directions, increasing order, first fastest
             int c[3] = {0, 0, 0};
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
                 if (k == m) continue;
                 const int qk = qdiv(L, rce[k]);
-                c[k] = L - qk * ext[k];
+                c[k] = L - m24(qk, ext[k]);
                 L = qk;
             }
-            const int bin = g * cap + c[0] + si1 * c[1] + si2 * c[2];
-            bout[u] = m == DIM - 1 ? g * nout + c[0] + sg1 * c[1] + sg2 * c[2]
-                                   : g * cap + c[0] + so1 * c[1] + so2 * c[2];
+            const int bin = m24(g, cap) + c[0] + m24(si1, c[1]) + m24(si2, c[2]);
+            bout[u] = m == DIM - 1 ? m24(g, nout) + c[0] + m24(sg1, c[1]) + m24(sg2, c[2])
+                                   : m24(g, cap) + c[0] + m24(so1, c[1]) + m24(so2, c[2]);
             // the tile's B operands first (up to 4 LDS reads in flight), then
             // the MFMAs; ks is wave-uniform
             double b[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int k = 4 * s + kq;
-                b[s] = (s < ks && ok[u] && k < ni) ? buf[bin + k * str_in] : 0.0;
+                b[s] = (s < ks && ok[u] && k < ni) ? buf[bin + m24(k, str_in)] : 0.0;
             }
 #pragma unroll
             for (int s = 0; s < 4; ++s)
@@ -340,9 +342,9 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
                 const int q = 4 * r + kq;
                 if (q >= no) continue;
                 if (m == DIM - 1)
-                    dst[bout[u] + q * str_g] = acc[u][r];
+                    dst[bout[u] + m24(q, str_g)] = acc[u][r];
                 else
-                    buf[bout[u] + q * str_out] = acc[u][r];
+                    buf[bout[u] + m24(q, str_out)] = acc[u][r];
             }
         }
         if (m < DIM - 1) __syncthreads();
