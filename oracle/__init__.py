@@ -7,6 +7,10 @@ and this package never imports the product package: the two share no code.
 Python side of ``oracle.c`` (plain FP64 C, see its header for the paper
 passages it follows).  Functions take and return numpy arrays in the layout
 ``u[v, e, node]`` with ``node = ix + n*iy + n*n*iz``.
+
+Parity unpinned by the paper: the Euler flux's logarithmic-mean mass flux and
+pressure average (the paper names the flux without printing it); everything
+that follows from them is pinned by the tests (see ``oracle.c``).
 """
 from __future__ import annotations
 

@@ -53,6 +53,14 @@
  * flux (cited in the Results section but not printed) in its published form,
  * with the logarithmic mean evaluated as (b-a)/log1p((b-a)/a).
  *
+ * Parity unpinned by the paper: two choices inside oracle_flux_euler, the
+ * logarithmic-mean mass flux and the pressure average {{rho}}/(2 {{beta}}),
+ * come from the flux's own literature, since the paper names the flux without
+ * printing it.  The tests pin everything that follows from them (symmetry,
+ * consistency with the physical flux, Tadmor's entropy-conservation identity,
+ * which fixes the energy flux, and the kinetic-energy-preserving momentum
+ * structure); the two choices themselves have no pin from the paper.
+ *
  * Layout of every state / output array:
  *     u[v * E * N + e * N + node],  node = ix + n*iy + n*n*iz,  N = n^d.
  * Euler variables in order (rho, rho*u, rho*v, rho*w, E).
