@@ -26,10 +26,14 @@
  *
  *   - The Remark after Eq. (5): the same Hadamard product with alpha = 0 and
  *     facet cubature nodes, the surface terms.  oracle_lagrange_endpoints and
- *     oracle_surface give its plain definition (see there).
+ *     oracle_surface give its plain definition (see there).  The facet
+ *     operator is a reading (the paper does not print it): parity unpinned
+ *     by the paper, pinned by the reading's invariants in the tests.
  *   - Curvilinear elements (the Results section's warped grids): the
  *     metric-averaged two-point flux in reference direction m,
  *     sum_k f_k(u_i, u_j) (Ja^m_k(i) + Ja^m_k(j)) / 2; oracle_curv_volume.
+ *     Also a reading (the paper names the grids, not the metric treatment):
+ *     parity unpinned by the paper, pinned by the reading's invariants.
  *   - Entropy projection (the Results section's uncollocated scheme uses
  *     it with the sum-factorized Hadamard products): facet states as the
  *     conserved variables of the facet-interpolated entropy variables,
