@@ -31,25 +31,37 @@ namespace dev {
 
 // a2..a5 for one line: every unordered pair (a < c) once plus the diagonal,
 // accumulated into t.  The loads of the stored arrays are rotated into the
-// frame of direction M.
-template <int N, class P, int M, class Op>
+// frame of direction M.  With AHEAD (the standalone volume kernel at n <= 8,
+// where the registers allow it) the next partner's loads are issued before
+// the current pair's arithmetic, so their LDS latency overlaps it.
+template <int N, class P, int M, bool AHEAD, class Op>
 __device__ __forceinline__ void line_pairs(const typename P::Real *le, int AS, int pbase, int pstride,
                                            const Op &op, const typename P::Consts &K, double gamma,
                                            typename P::Real (&t)[N][P::NV]) {
     using R = typename P::Real;
+    using Node = typename P::Node;
+    // node k of the line sits at byte offset pb + k * ps from le; the offset
+    // is made opaque at each use, so the compiler re-reads the node from LDS
+    // instead of keeping the whole line live in registers
+    const int pb = pbase * (int)sizeof(R), ps = pstride * (int)sizeof(R);
+    auto at = [&](int k) {
+        return reinterpret_cast<const R *>(reinterpret_cast<const char *>(le) + pin(pb + k * ps));
+    };
 #pragma unroll
     for (int a = 0; a < N; ++a) {
-        const typename P::Node A = P::load(le, AS, pin(pbase + a * pstride), M);
+        const Node A = P::load(at(a), AS, 0, M);
         R F[P::NV];
         P::diag(A, gamma, F);
         const R qaa = (R)op.q(a * N + a);
 #pragma unroll
         for (int k = 0; k < P::NV; ++k) t[a][k] = qaa * F[k] + t[a][k];
+        Node C;
+        if (AHEAD && a + 1 < N) C = P::load_partner(at(a + 1), AS, 0, M);
 #pragma unroll
         for (int c = a + 1; c < N; ++c) {
-            // re-read node c from LDS for every pair: an opaque index stops
-            // the compiler from keeping the whole line live in registers
-            const typename P::Node C = P::load_partner(le, AS, pin(pbase + c * pstride), M);
+            Node Cn;
+            if (!AHEAD) C = P::load_partner(at(c), AS, 0, M);
+            else if (c + 1 < N) Cn = P::load_partner(at(c + 1), AS, 0, M);
             P::pair(A, C, K, F);
             const R qac = (R)op.q(a * N + c), qca = (R)op.q(c * N + a);
 #pragma unroll
@@ -57,13 +69,14 @@ __device__ __forceinline__ void line_pairs(const typename P::Real *le, int AS, i
                 t[a][k] = qac * F[k] + t[a][k];
                 t[c][k] = qca * F[k] + t[c][k];
             }
-            // one pair in flight at a time: its sums complete here, before
-            // the next pair's loads (ordered after this fence) are issued
+            // one pair's arithmetic in flight at a time: its sums complete
+            // here, before the loads ordered after this fence are issued
 #pragma unroll
             for (int k = 0; k < P::NV; ++k) {
                 t[a][k] = pin(t[a][k]);
                 t[c][k] = pin(t[c][k]);
             }
+            if (AHEAD && c + 1 < N) C = Cn;
         }
     }
 }
@@ -128,14 +141,17 @@ struct TableOp {
 // The per-line work of a block.  VolumeWork is a2..a5 (every pair of the
 // line); SurfaceWork is the facet part of the surface term (below);
 // VolumeSurfaceWork does both into the same line sums.
-struct VolumeWork {
+template <bool AHEAD>
+struct VolumeWorkT {
     template <int M, int N, class P, class Op, class R>
     __device__ __forceinline__ void lines(const R *le, int AS, int pbase, int pstride, const Op &op,
                                           const typename P::Consts &K, double gamma, R (&t)[N][P::NV], int64_t,
                                           int, double, const double *) const {
-        line_pairs<N, P, M>(le, AS, pbase, pstride, op, K, gamma, t);
+        line_pairs<N, P, M, AHEAD && N <= 8>(le, AS, pbase, pstride, op, K, gamma, t);
     }
 };
+using VolumeWork = VolumeWorkT<false>;       // serving and curvilinear kernels (register-capped)
+using VolumeWorkAhead = VolumeWorkT<true>;   // the standalone volume kernel
 
 // One block of EPB elements starting at element e0 of an E-element mesh:
 // steps a1..a6 with the line work of `work`.  lds holds SfLayout::LDS_D

@@ -18,10 +18,11 @@ sf_volume_kernel(const VolArgs<N> args) {
     __shared__ double sref[L::REF_D];
     const int64_t e0 = (int64_t)blockIdx.x * Geom<N, DIM>::EPB;
     if constexpr (N <= 9) {
-        sf_block<N, DIM, P>(args.u, args.out, args.E, e0, ParamOp<N>{args.op}, args.gamma, lds, sref);
+        sf_block<N, DIM, P>(args.u, args.out, args.E, e0, ParamOp<N>{args.op}, args.gamma, lds, sref,
+                            VolumeWorkAhead{});
     } else {
         const auto A = kernel_args<VolArgs<N>>();
-        sf_block<N, DIM, P>(A->u, A->out, A->E, e0, KernargOp<N>{&A->op}, A->gamma, lds, sref);
+        sf_block<N, DIM, P>(A->u, A->out, A->E, e0, KernargOp<N>{&A->op}, A->gamma, lds, sref, VolumeWorkAhead{});
     }
 }
 
