@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -52,11 +53,24 @@ KERNEL_SOURCES = [os.path.join("paper_2306_11665_amd", "csrc", f)
                  [os.path.join("paper_2306_11665_amd", "build.py")]
 
 
+def _code_only(text: str, c_family: bool) -> str:
+    """The source without comments and blank lines (C/C++ // and /* */
+    comments, or Python # comments), so that editing a comment does not mark
+    the profiled kernel as changed.  String literals holding comment markers
+    are not expected in these files."""
+    if c_family:
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+    else:
+        text = re.sub(r"(?m)^\s*#[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(_code_only(f.read(), not rel.endswith(".py")).encode())
     return h.hexdigest()[:16]
 
 

@@ -138,9 +138,9 @@ struct TableOp {
     __device__ double w(int i) const { return W[i]; }
 };
 
-// The per-line work of a block.  VolumeWork is a2..a5 (every pair of the
-// line); SurfaceWork is the facet part of the surface term (below);
-// VolumeSurfaceWork does both into the same line sums.
+// The per-line work of a block.  VolumeWorkT is a2..a5 (every pair of the
+// line); SurfaceWork (with the surface kernels) is the facet part of the
+// surface term, and with VOLUME it adds the pairs into the same line sums.
 template <bool AHEAD>
 struct VolumeWorkT {
     template <int M, int N, class P, class Op, class R>
