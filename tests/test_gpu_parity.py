@@ -178,13 +178,17 @@ def test_dense_gpu_path(torch_dev, sf, orc, flux, d, n):
     assert mx.max() <= TOL64, mx
 
 
-@pytest.mark.parametrize("n", [2, 4, 5, 8])
-def test_fp32split_small(torch_dev, sf, orc, n):
-    u = state("euler", 9, n, 3, seed=400 + n)
-    y = run_gpu(torch_dev, sf, u, n, 3, "euler", precision="fp32_split")
-    ref = orc.dense_volume(u, n, 3, "euler")
+@pytest.mark.parametrize("nodes", ["gl", "gll"])
+@pytest.mark.parametrize("n", list(range(2, 14)))
+def test_fp32split_all_n(torch_dev, sf, orc, n, nodes):
+    """The FP32-split form at every built n and both node sets (ragged
+    element counts), against the FP64 dense oracle at the form's tolerance."""
+    E = 9 if n <= 6 else 3
+    u = state("euler", E, n, 3, seed=400 + n)
+    y = run_gpu(torch_dev, sf, u, n, 3, "euler", nodes=nodes, precision="fp32_split")
+    ref = orc.dense_volume(u, n, 3, "euler", nodes_kind=nodes)
     mx, _ = normwise(y, ref)
-    assert mx.max() <= TOL32, mx
+    assert mx.max() <= TOL32, (n, nodes, mx)
 
 
 # ------------------------------------------------------------- edge cases
