@@ -19,7 +19,9 @@ def env():
 def test_served_result_equals_direct_call(env, orc):
     torch, serving, sfhad, W = env
     with serving.Server(1 << 30, max_inflight=16) as srv:
-        for n, E, nodes in [(3, 37, "gl"), (5, 101, "gll"), (8, 40, "gl")]:
+        cases = [(n, E, nodes) for n, E in [(2, 129), (3, 37), (4, 65), (5, 101), (6, 23), (7, 11), (8, 40)]
+                 for nodes in ("gl", "gll")]
+        for n, E, nodes in cases:
             u = W.euler_state(E, n, seed=1200 + n, freestream_frac=0.1)
             m = srv.register(u, n, nodes)
             for prec in ("fp64", "fp32_split"):
