@@ -265,3 +265,27 @@ def test_tensor_rect_validation(sf):
     assert f(None, 0, 4, 6, 3, 5, Mp, None, None) == 0            # E = 0
     assert L.sf_basis_rect(5, 4, 0, None, None) == -1              # m < n
     assert L.sf_basis_rect(4, 17, 0, None, None) == -2
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without libsfhad.so every binding call raises: there is no CPU
+    fallback (checked in a fresh interpreter with the library path pointed
+    at a file that does not exist)."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2306_11665_amd import sfhad\n"
+        "sfhad.LIB_PATH = %r\n"
+        "for call in (lambda: sfhad.lib(), lambda: sfhad.operator_1d(4), lambda: sfhad.basis_1d(4)):\n"
+        "    try:\n"
+        "        call()\n"
+        "    except RuntimeError as e:\n"
+        "        assert 'not built' in str(e)\n"
+        "    else:\n"
+        "        raise SystemExit('a call succeeded without the library')\n"
+        "print('raised')\n"
+    ) % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))), str(tmp_path / "absent.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "raised"
