@@ -210,6 +210,38 @@ def fig1_leg(torch, sfhad, W, stream) -> dict:
             "fit": "least squares over n = 6..16", "paper_slopes": {"sf": 4, "dense": 6}}
 
 
+def per_n_leg(torch, sfhad, ut, stream, steps: int) -> dict:
+    """The FP64 and FP32-split Euler volume kernels for every built n on the
+    same number of nodes (the n = 8 state's 16.8 M nodes of per-node random
+    states, regrouped into E = 16.8 M / n^3 elements): DOF/s and the modelled
+    FP64 lane-operation rate as a fraction of the 2.4 GHz issue peak, the same
+    model the headline roofline uses."""
+    flat = ut.reshape(5, -1)
+    rows = []
+    for n in range(3, 14):
+        En = flat.shape[1] // n ** 3
+        un = flat[:, : En * n ** 3].reshape(5, En, n ** 3).contiguous()
+        on = torch.empty_like(un)
+        row = {"n": n, "elements": En}
+        for prec in ("fp64", "fp32_split"):
+            def stepn():
+                sfhad.volume(un, n, 3, "euler", out=on, stream=stream, precision=prec)
+
+            for _ in range(3):
+                stepn()
+            _, k = timed_launches(torch, stepn, steps, stream)
+            frac = model_ops_per_element(n) * En / (k * 1e-3) / PEAK_FP64_LANE_OPS
+            row[prec] = {"kernel_ms": round(k, 5), "dof_per_s": 5 * En * n ** 3 / (k * 1e-3),
+                         "model_issue_frac": round(frac, 4)}
+        rows.append(row)
+        log(f"[bench] per-n n={n:2d} E={En:6d}: fp64 {row['fp64']['kernel_ms'] * 1e3:8.1f} us "
+            f"frac {row['fp64']['model_issue_frac']:.3f} | fp32-split {row['fp32_split']['kernel_ms'] * 1e3:8.1f} us "
+            f"({row['fp64']['kernel_ms'] / row['fp32_split']['kernel_ms']:.2f}x)")
+        del un, on
+    return {"what": "3D Euler volume term on 16.8 M nodes of random per-node states for every n, "
+                    "kernel time per launch (HIP events)", "rows": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,7 +254,7 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per offered load")
     ap.add_argument("--legs", default="all",
                     help="comma list of extra legs (fp32, dense, tensor, surface, curvilinear, entropy, uncollocated, graph, "
-                         "figure1, serving) or 'all'")
+                         "per_n, figure1, serving) or 'all'")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain device-to-device copy of the input's size (counter calibration)")
     args = ap.parse_args()
@@ -553,6 +585,9 @@ def main() -> int:
                                              "dof_per_s": w2.dof / (per_launch * 1e-3),
                                              "elem_evals_per_s": w2.E / (per_launch * 1e-3)}
             log(f"[bench] n=4 E=4096 in a graph: {per_launch * 1e3:.2f} us/launch")
+
+    if not args.no_extras and want("per_n"):
+        result["per_n"] = per_n_leg(torch, sfhad, ut, stream, max(5, args.steps // 5))
 
     if not args.no_extras and want("figure1"):
         f1 = fig1_leg(torch, sfhad, W, stream)

@@ -34,8 +34,17 @@
  *    thread-local detail string for the last failing call on that thread.
  *  - Non-physical Euler states (rho <= 0 or p <= 0) are outside the domain:
  *    the result is unspecified (NaN/Inf propagate) and nothing is checked on
- *    the device.  The kernels assume rho and beta = rho/(2p) in about
- *    [1e-30, 1e30] (products of up to four such means are formed).
+ *    the device.  Domain of the Euler kernels (tested at its ends):
+ *      FP64:        rho and beta = rho/(2p) in about [1e-30, 1e30] (products
+ *                   of up to three such means are formed);
+ *      FP32-split:  rho and beta in about [1e-10, 1e10] (FP32 products of up
+ *                   to three means);
+ *    any ratio of rho or beta between the nodes of one element: the per-node
+ *    logarithms are taken against the element's first node, and the FP64
+ *    logarithmic mean's relative error grows as
+ *    eps (|ln(a/a_0)| + |ln(b/a_0)| + 2) / |ln a - ln b| (a_0 the first
+ *    node's value), below about 3e-12 per pair for in-element ratios up to
+ *    1e6 (measured: within 1e-12 normwise per element up to 1e6).
  *  - Thread safety: the operator cache is mutex-protected; calls on distinct
  *    streams are independent.
  */
@@ -304,11 +313,19 @@ int sf_server_sim_fail_launches(sf_server *srv, int count);
  * use (any pointer may be NULL). */
 int sf_server_stats(sf_server *srv, int64_t *queued, int64_t *inflight, int64_t *budget_used);
 
+/* Since creation: batches launched, the most requests packed into one
+ * batch, and the most launch slots running at once (2 means a batch started
+ * while the previous one was still on the device).  Any pointer may be NULL. */
+int sf_server_batch_stats(sf_server *srv, int64_t *batches, int64_t *max_batch_requests,
+                          int64_t *max_slots_busy);
+
 /* Register a mesh: the state (layout as above; Euler flux, d = 3,
  * 2 <= n <= 8, gamma = 1.4) is copied to a device buffer the server owns.
- * u_host points to host memory.  Returns SF_ERR_UNSUPPORTED for other fluxes
- * or n. */
-int sf_mesh_register(sf_server *srv, const double *u_host, int64_t elem_count, int n,
+ * u_host_or_dev points to host memory or to device memory of this GPU (the
+ * runtime tells them apart); the copy completes before the call returns, so
+ * the caller may free or reuse it then.  Returns SF_ERR_UNSUPPORTED for
+ * other fluxes or n. */
+int sf_mesh_register(sf_server *srv, const double *u_host_or_dev, int64_t elem_count, int n,
                      int flux_kind, int node_kind, sf_mesh *out);
 
 /* Submit one residual evaluation of a registered mesh (non-blocking).

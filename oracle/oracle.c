@@ -461,7 +461,6 @@ int oracle_sf_volume(const double *u, long E, int n, int d, int flux,
     return 0;
 }
 
-/* Thread count OpenMP will use (1 without OpenMP). */
 /* ------------------------------------------------------------------------ */
 /* Basis transformation (Eq. (6), proof of Theorem 1)                        */
 /* ------------------------------------------------------------------------ */
@@ -872,6 +871,7 @@ int oracle_surface(const double *u, const double *uf, long E, int n, int d, int 
     return 0;
 }
 
+/* Thread count OpenMP will use (1 without OpenMP). */
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

@@ -56,16 +56,70 @@ __device__ __forceinline__ kernarg_ptr<T> kernel_args() {
     return (kernarg_ptr<T>)__builtin_amdgcn_kernarg_segment_ptr();
 }
 
-template <int N, int DIM>
+// Lane mapping of a block.  FE = 0 ("grouped"): d groups of LPD lanes,
+// group m taking every line of direction m of the block's EPB elements, so
+// that each wave works on one direction.  FE > 0 ("flat"): FE elements per
+// block and their d n^(d-1) lines of every direction laid out one after the
+// other over the block's lanes (element, then direction, then line), so
+// that a wave may hold lines of several directions; the flux code then
+// takes the direction as a per-lane value.  The flat mapping fills the
+// lanes when n^(d-1) does not divide into 64 (n = 6, 9, 12, ...).
+template <int N, int DIM, int FE = 0>
 struct Geom {
     static constexpr int LINES = DIM == 3 ? N * N : N;       // lines per direction per element
     static constexpr int NODES = LINES * N;                  // n^d
-    static constexpr int EPB = LINES >= 64 ? 1 : 64 / LINES; // elements per block
-    static constexpr int LPD = ((EPB * LINES + 63) / 64) * 64;  // lanes per direction group
-    static constexpr int THREADS = DIM * LPD;
+    static constexpr int EPB = FE > 0 ? FE : (LINES >= 64 ? 1 : 64 / LINES);  // elements per block
+    static constexpr int LPD = ((EPB * LINES + 63) / 64) * 64;  // lanes per direction group (grouped)
+    static constexpr int LANES = FE > 0 ? EPB * DIM * LINES : DIM * LPD;  // lanes with a line (flat: all)
+    static constexpr int THREADS = FE > 0 ? ((LANES + 63) / 64) * 64 : DIM * LPD;
     static constexpr int PADN = NODES + NODES / N;           // padded array length per element
     __host__ __device__ static constexpr int pidx(int node) { return node + node / N; }
+    // (element in block, direction, line) of lane tid; el >= EPB for idle lanes
+    __device__ static void lane(int tid, int &el, int &m, int &line) {
+        if (FE > 0) {
+            el = tid / (DIM * LINES);
+            const int rem = tid - el * (DIM * LINES);
+            m = rem / LINES;
+            line = rem - m * LINES;
+        } else {
+            m = tid / LPD;
+            const int r = tid - m * LPD;
+            el = r / LINES;
+            line = r - el * LINES;
+        }
+    }
 };
+
+// Launch shape of the standalone 3D Euler volume kernels: elements per block
+// of the flat mapping (0: the grouped mapping), the minimum number of waves
+// per SIMD the register budget must allow (1: no bound), and whether the
+// next partner node is loaded one pair ahead.  Measured on MI355X (n = 8
+// state regrouped into n^3-node elements, against the grouped mapping):
+//   n = 5:  FP64 3 elements per 4-wave block (225 of 256 lanes, grouped 50/64)
+//           without the look-ahead load (126 VGPRs, 4 waves per SIMD): 1.08x;
+//           FP32-split grouped without it: 1.08x;
+//   n = 6:  2 elements per 4-wave block (216/256, grouped 36/64): 1.29x FP64,
+//           1.22x FP32-split;
+//   n = 9:  one element per 4-wave block (243/256, grouped 81/128), FP64 held
+//           to 3 waves per SIMD: 2.0x;
+//   n = 12, 13: one element per 7- and 8-wave block (432/448, 507/512): 1.5x
+//           and 1.6x (the grouped 9-wave blocks had to spill to fit).
+// n = 2, 3, 4, 8 fill their waves grouped.  Flat blocks of 5 or 6 waves
+// (n = 5 with 5 elements, n = 6 with 3, n = 7 with 2, n = 10) ran as if only
+// one block fitted per CU, and bounding registers below the natural count
+// (spilling) was slower, so n = 7, 10, 11 stay grouped.
+struct VolumeShape {
+    int fe;
+    int min_waves;
+    bool ahead;
+};
+constexpr VolumeShape euler_volume_shape(int n, bool fp64) {
+    return n == 5 ? VolumeShape{fp64 ? 3 : 0, 1, false}
+         : n == 6 ? VolumeShape{2, 1, true}
+         : n == 9 ? VolumeShape{1, fp64 ? 3 : 1, false}
+         : (n == 12 || n == 13) ? VolumeShape{1, 1, false}
+         : VolumeShape{0, 1, n <= 8};
+}
 
 // Padded LDS base index and stride of line `line` in direction m
 // (see the padded index node + node / N).
@@ -116,21 +170,23 @@ __device__ __forceinline__ double rcp_fine(double x) {
     return __builtin_fma(r, __builtin_fma(e, e, e), r);
 }
 
-// ln(1 + x) for finite x > -1, to about one ulp, without a library call.
-// 1 + x = u + e exactly (two-sum); u = 2^k m with m in [sqrt(1/2), sqrt(2));
-// ln(1 + x) = k ln 2 + ln m + e/u.  With f = m - 1 (exact) and s = f/(2 + f),
+// ln(u + e) for a normal u > 0 and a correction |e| <= ulp(u), to about one
+// ulp, without a library call.  u = 2^k m with m in [sqrt(1/2), sqrt(2));
+// ln(u + e) = k ln 2 + ln m + e/u.  With f = m - 1 (exact) and s = f/(2 + f),
 // ln m = 2 atanh(s) = f - f^2/2 + s (f^2/2 + R(s^2)), R(z) = sum_j 2 z^j/(2j+1)
 // (|s| <= 0.1716, so nine terms leave a truncation below 1e-17 of ln m); the
 // f - f^2/2 grouping keeps the rounding of s and R out of the leading terms.
-// ln 2 is split so that k * kLn2Hi is exact for |k| < 2^11.
+// ln 2 is split so that k * kLn2Hi is exact for |k| < 2^11.  FINE_CORR
+// refines the reciprocal of e/u to full precision: needed when e is
+// comparable to the result (ln(1 + x) for |x| near eps), not when only the
+// absolute error matters (e/u <= 2^-52, so a 2^-22 reciprocal estimate
+// leaves an error below 2^-74).
 constexpr double kLn2Hi = 0.6931471805598903;      // 42 leading bits of ln 2
 constexpr double kLn2Lo = 5.497923018708371e-14;   // ln 2 - kLn2Hi
 constexpr double kSqrtHalf = 0.7071067811865476;
 
-__device__ __forceinline__ double log1p_series(double x) {
-    const double u = 1.0 + x;
-    const double bv = u - 1.0;
-    const double e = (1.0 - (u - bv)) + (x - bv);  // 1 + x = u + e exactly
+template <bool FINE_CORR>
+__device__ __forceinline__ double log_core(double u, double e) {
     int k = __builtin_amdgcn_frexp_exp(u);
     double m = __builtin_amdgcn_frexp_mant(u);     // u = m 2^k, m in [0.5, 1)
     if (m < kSqrtHalf) {
@@ -153,10 +209,30 @@ __device__ __forceinline__ double log1p_series(double x) {
     const double hf = 0.5 * f * f;
     const double lnm = f - (hf - s * (hf + R));
     const double kd = (double)k;
-    // e / u: for |x| near eps, e is comparable to the result, so the
-    // reciprocal is refined to full precision
-    const double corr = __builtin_amdgcn_ldexp(e, -k) * rcp_fine(m);
+    const double corr = __builtin_amdgcn_ldexp(e, -k) * (FINE_CORR ? rcp_fine(m) : __builtin_amdgcn_rcp(m));
     return __builtin_fma(kd, kLn2Hi, lnm + __builtin_fma(kd, kLn2Lo, corr));
+}
+
+// ln(1 + x) for finite x > -1, to about one ulp: 1 + x = u + e exactly
+// (two-sum), then ln(u + e).
+__device__ __forceinline__ double log1p_series(double x) {
+    const double u = 1.0 + x;
+    const double bv = u - 1.0;
+    const double e = (1.0 - (u - bv)) + (x - bv);
+    return log_core<true>(u, e);
+}
+
+// ln(x ix0) for positive normal x and ix0 (the reciprocal of a reference
+// value x0): the product is split exactly, x ix0 = q + e (q rounded, e by
+// one FMA), and ln(q + e) taken as above.  The absolute error is about
+// eps |ln(x ix0)| plus the rounding of ix0, a relative error delta that
+// adds the same ln(1 + delta) to the logarithm of every x against this ix0:
+// differences ln(x_a ix0) - ln(x_b ix0) = ln x_a - ln x_b keep an absolute
+// error of about eps (|ln(x_a/x0)| + |ln(x_b/x0)|), at any ratio x/x0.
+__device__ __forceinline__ double log_ratio(double x, double ix0) {
+    const double q = x * ix0;
+    const double e = __builtin_fma(x, ix0, -q);
+    return log_core<false>(q, e);
 }
 
 // ---------------------------------------------------------------------------
@@ -209,30 +285,38 @@ struct ScalarFlux {
 
 // ---------------------------------------------------------------------------
 // Chandrashekar's entropy-conserving, kinetic-energy-preserving Euler flux,
-// FP64.  Stored per node: rho, half velocities w = v/2 (a sum of two stored
-// values is a mean velocity), beta = rho/(2p), and the logarithms of rho and
-// beta relative to the element's first node,
-//     lr = ln(rho / rho_0) = log1p((rho - rho_0)/rho_0),
-//     lb = cg ln(beta / beta_0),     cg = 1/(2(gamma-1)),
-// so that their rounding error is about eps |ln(a / a_0)|, i.e. scales with
-// the element's own variation rather than with |ln a|.  A lane works in the
-// frame of its line, (n, t1, t2) = (m, m+1, m+2) mod 3, so the flux code has
-// no direction branches; accumulators are (rho, n-, t1-, t2-momentum, E).
+// FP64.  Stored per node: half the density r = rho/2 (a sum of two stored
+// values is the mean {{rho}}), half velocities w = v/2 (a sum is a mean
+// velocity), beta = rho/(2p), and the logarithms
+//     lr = ln(rho / rho_0) / 2,     lb = cg ln(beta / beta_0),
+// cg = 1/(2(gamma-1)), against the element's first node (rho_0, beta_0;
+// log_ratio), so that their rounding error is about eps |ln(a / a_0)|,
+// i.e. scales with the element's own variation rather than with |ln a|.  A
+// lane works in the frame of its line, (n, t1, t2) = (m, m+1, m+2) mod 3, so
+// the flux code has no direction branches; accumulators are (rho, n-, t1-,
+// t2-momentum, E).
 //
 // Logarithmic means a^ln = (a - b)/(ln a - ln b) are carried as a fraction
-// N/D.  With s = a + b, d = a - b:
-//   u = d^2/s^2 >= 1e-6:  N = d,      D = lr_a - lr_b  (a difference of
-//                         stored relative logarithms)
-//   u < 1e-6:             N = s^3/2,  D = s^2 + d^2 (1/3 + u/5),
-// (the switch is tested on |lr_a - lr_b| < 2e-3, which is |f| < tanh(1e-3)),
-//                         i.e. s^2 times the series of atanh(f)/f, f = d/s
-//                         (truncation u^3/7 < 1.5e-19; exact equality gives a).
-// The direct form's error, about eps (|ln(a/a_0)| + |ln(b/a_0)|) / |2f|, is
-// below 2 eps/|2f| of the element's own flux variation (~1e-13 at the
-// threshold |f| = 1e-3), for smooth and rough data alike.  The near-equal
-// case is a real branch that waves with no near-equal lane skip.
-// The three quotients the flux needs -- rho^ln = Nr/Dr, 1/beta^ln = Db/Nb
-// and p_hat = {{rho}}/(2{{beta}}) -- share one reciprocal 1/(Dr Nb s_beta).
+// N/D.  For rho, in halves (s = r_a + r_b, d = r_a - r_b, u = d^2/s^2):
+//   direct:        N = d,        D = lr_a - lr_b  (= (ln rho_a - ln rho_b)/2)
+//   near-equal:    N = s^3,      D = s^2 + d^2 (1/3 + u/5),
+// for beta (s = b_a + b_b, d = b_a - b_b), carrying cg / beta^ln = D/N:
+//   direct:        N = d,        D = lb_a - lb_b
+//   near-equal:    N = s^3/2,    D = cg (s^2 + d^2 (1/3 + u/5)).
+// The near-equal form is s times the series of f/atanh(f), f = d/s (the
+// truncation u^3/7 is below 1.5e-19 for u < 1e-6; exact equality gives the
+// mean exactly); it is taken when |ln a - ln b| < 2e-3, i.e.
+// |f| = tanh(|ln a - ln b| / 2) < ~1e-3, tested on the stored logarithms
+// (one compare, no multiply).  The direct form's relative error is about
+// eps (|ln(a/a_0)| + |ln(b/a_0)| + 2) / |ln a - ln b|: below about 1e-13 at
+// the switch for an element whose values stay within a factor e of its first
+// node's, and growing with the logarithm of the in-element ratio (about
+// 3e-12 at the switch for ratios of 1e6).  The near-equal case is a real
+// branch that waves with no near-equal lane skip.
+// The three quotients the flux needs -- rho^ln = Nr/Dr, cg/beta^ln = Db/Nb
+// and p_hat = {{rho}}/(2{{beta}}) = s_r/s_b -- share one reciprocal
+// R = 1/(Dr Nb s_b): each quotient is its numerator times R times the other
+// two factors, formed as pairwise products.
 // Valid for rho, beta in about [1e-30, 1e30].
 // ---------------------------------------------------------------------------
 struct EulerNode {
@@ -244,41 +328,44 @@ struct EulerFP64 {
     static constexpr int NV = 5;
     static constexpr int NS = 7;
     static constexpr int NX = 0;
-    static constexpr int NREF = 4;  // rho_0, 1/rho_0, beta_0, 1/beta_0
+    static constexpr int NREF = 2;  // 1/rho_0, 1/beta_0
     enum { S_R = 0, S_W = 1, S_B = 4, S_LR = 5, S_LB = 6 };
     using Node = EulerNode;
     // Series branch when |ln a - ln b| < kLogTau, i.e. |a - b|/(a + b) =
-    // tanh(|ln a - ln b| / 2) < ~1e-3 (u = f^2 < 1e-6); tested on the stored
-    // relative logarithms (one compare, no multiply).
+    // tanh(|ln a - ln b| / 2) < ~1e-3 (u = f^2 < 1e-6).
     static constexpr double kLogTau = 2e-3;
+
+    // rho, beta = rho/(2p) of a conserved state; returns 1/rho, sets v
+    __device__ static double primitives(const double *uc, double gamma, double (&v)[3], double &beta) {
+        const double r = uc[0];
+        const double ir = rcp_fine(r);
+        v[0] = uc[1] * ir;
+        v[1] = uc[2] * ir;
+        v[2] = uc[3] * ir;
+        const double p = (gamma - 1.0) * (uc[4] - 0.5 * r * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+        beta = 0.5 * r * rcp_fine(p);
+        return ir;
+    }
 
     // The element's reference values, from its first node's conserved state.
     __device__ static void make_ref(const double *uc, double gamma, double *ref) {
-        const double r = uc[0];
-        const double ir = rcp_fine(r);
-        const double v0 = uc[1] * ir, v1 = uc[2] * ir, v2 = uc[3] * ir;
-        const double p = (gamma - 1.0) * (uc[4] - 0.5 * r * (v0 * v0 + v1 * v1 + v2 * v2));
-        const double b = 0.5 * r * rcp_fine(p);
-        ref[0] = r;
-        ref[1] = ir;
-        ref[2] = b;
-        ref[3] = rcp_fine(b);
+        double v[3], b;
+        ref[0] = primitives(uc, gamma, v, b);
+        ref[1] = rcp_fine(b);
     }
 
     // a1: conserved -> stored quantities (FP64, per node).
     __device__ static void stage(const double *uc, const double *ref, double gamma, double *s) {
+        double v[3], b;
+        primitives(uc, gamma, v, b);
         const double r = uc[0];
-        const double ir = rcp_fine(r);
-        const double v0 = uc[1] * ir, v1 = uc[2] * ir, v2 = uc[3] * ir;
-        const double p = (gamma - 1.0) * (uc[4] - 0.5 * r * (v0 * v0 + v1 * v1 + v2 * v2));
-        const double b = 0.5 * r * rcp_fine(p);
-        s[S_R] = r;
-        s[S_W + 0] = 0.5 * v0;
-        s[S_W + 1] = 0.5 * v1;
-        s[S_W + 2] = 0.5 * v2;
+        s[S_R] = 0.5 * r;
+        s[S_W + 0] = 0.5 * v[0];
+        s[S_W + 1] = 0.5 * v[1];
+        s[S_W + 2] = 0.5 * v[2];
         s[S_B] = b;
-        s[S_LR] = log1p_series((r - ref[0]) * ref[1]);
-        s[S_LB] = (0.5 / (gamma - 1.0)) * log1p_series((b - ref[2]) * ref[3]);
+        s[S_LR] = 0.5 * log_ratio(r, ref[0]);
+        s[S_LB] = (0.5 / (gamma - 1.0)) * log_ratio(b, ref[1]);
     }
 
     // Load node at padded index idx of one element's arrays (arrays are
@@ -303,25 +390,27 @@ struct EulerFP64 {
 
     // Constants of the pair flux, in scalar registers for the whole kernel
     // (64-bit values that are not inline operands would otherwise be rebuilt
-    // for every pair).  thr_b carries the cg folded into the stored ln beta.
+    // for every pair).  thr_r is on the halved ln rho, thr_b carries the cg
+    // folded into the stored ln beta.
     struct Consts {
         double cg, c3, c5, thr_r, thr_b;
     };
     __device__ static Consts consts(double cg) {
-        return Consts{uniform_f64(cg), uniform_f64(1.0 / 3.0), uniform_f64(0.2), uniform_f64(kLogTau),
+        return Consts{uniform_f64(cg), uniform_f64(1.0 / 3.0), uniform_f64(0.2), uniform_f64(0.5 * kLogTau),
                       uniform_f64(kLogTau * cg)};
     }
 
-    // a4: two-point flux f_n(A, C) in the line frame (cg is folded into lb).
-    __device__ static void pair(const Node &A, const Node &C, const Consts &K, double *F) {
-        const double dr = A.r - C.r, sr = A.r + C.r;
-        const double db = A.b - C.b, sb = A.b + C.b;
+    // The three quotients of a pair: rho^ln, cg/beta^ln and p_hat.
+    __device__ static void means(const Node &A, const Node &C, const Consts &K, double &rho_ln, double &cgib,
+                                 double &phat) {
+        const double sr = A.r + C.r, dr = A.r - C.r;   // {{rho}}, (rho_a - rho_b)/2
+        const double sb = A.b + C.b, db = A.b - C.b;   // 2 {{beta}}, beta_a - beta_b
         double Nr = dr, Dr = A.lr - C.lr;
         double Nb = db, Db = A.lb - C.lb;
         if (__builtin_fabs(Dr) < K.thr_r) {  // near-equal densities: series
             const double dr2 = dr * dr, sr2 = sr * sr;
             const double u = dr2 * __builtin_amdgcn_rcp(sr2);
-            Nr = pin(0.5 * sr * sr2);
+            Nr = pin(sr * sr2);
             Dr = __builtin_fma(dr2, __builtin_fma(u, K.c5, K.c3), sr2);
         }
         if (__builtin_fabs(Db) < K.thr_b) {  // near-equal beta: series, times cg
@@ -330,12 +419,17 @@ struct EulerFP64 {
             Nb = pin(0.5 * sb * sb2);
             Db = K.cg * __builtin_fma(db2, __builtin_fma(u, K.c5, K.c3), sb2);
         }
-        const double DrNb = Dr * Nb;
-        const double R = rcp_fine(DrNb * sb);
-        const double rho_ln = Nr * (Nb * sb) * R;
-        const double cg_ibeta_ln = Db * (Dr * sb) * R;   // cg / beta^ln
-        const double phat = (0.5 * sr) * DrNb * R;      // {{rho}} / (2 {{beta}})
+        const double P1 = Nb * sb, P2 = Dr * sb, P3 = Dr * Nb;
+        const double R = rcp_fine(Dr * P1);
+        rho_ln = Nr * (P1 * R);
+        cgib = Db * (P2 * R);       // cg / beta^ln
+        phat = sr * (P3 * R);       // {{rho}} / (2 {{beta}})
+    }
 
+    // a4: two-point flux f_n(A, C) in the line frame (cg is folded into lb).
+    __device__ static void pair(const Node &A, const Node &C, const Consts &K, double *F) {
+        double rho_ln, cgib, phat;
+        means(A, C, K, rho_ln, cgib, phat);
         const double vn = A.wn + C.wn, v1 = A.wt1 + C.wt1, v2 = A.wt2 + C.wt2;     // {{v}}
         const double ww = __builtin_fma(A.wn, C.wn, __builtin_fma(A.wt1, C.wt1, A.wt2 * C.wt2));  // v_L.v_R / 4
         const double F0 = rho_ln * vn;
@@ -344,21 +438,23 @@ struct EulerFP64 {
         F[2] = F0 * v1;
         F[3] = F0 * v2;
         // F^E = F^rho [1/(2(gamma-1) beta^ln) + v_L.v_R/2] + p_hat {{v_n}}
-        F[4] = __builtin_fma(F0, __builtin_fma(2.0, ww, cg_ibeta_ln), phat * vn);
+        F[4] = __builtin_fma(F0, __builtin_fma(2.0, ww, cgib), phat * vn);
     }
 
-    // Physical flux f_n(u) (the pair flux at equal states), from stored data.
+    // Physical flux f_n(u) (the pair flux at equal states), from stored data
+    // (r = rho/2, w = v/2): p = r/beta, rho v_n = 4 r w_n,
+    // (E + p) v_n = 2 w_n (gamma/(gamma-1) p + 4 r |w|^2).
     __device__ static void diag(const Node &A, double gamma, double *F) {
-        const double p = 0.5 * A.r * rcp_fine(A.b);
-        const double vn = A.wn + A.wn, v1 = A.wt1 + A.wt1, v2 = A.wt2 + A.wt2;
-        const double rvn = A.r * vn;
-        const double q = __builtin_fma(vn, vn, __builtin_fma(v1, v1, v2 * v2));
-        F[0] = rvn;
-        F[1] = __builtin_fma(rvn, vn, p);
-        F[2] = rvn * v1;
-        F[3] = rvn * v2;
-        // (E + p) v_n with E + p = gamma/(gamma-1) p + rho |v|^2 / 2
-        F[4] = vn * __builtin_fma(gamma / (gamma - 1.0), p, 0.5 * A.r * q);
+        const double p = A.r * rcp_fine(A.b);
+        const double rw = A.r * A.wn;
+        const double F0 = 4.0 * rw;
+        const double G = 8.0 * rw;                       // rho v_n * 2
+        const double q = __builtin_fma(A.wn, A.wn, __builtin_fma(A.wt1, A.wt1, A.wt2 * A.wt2));
+        F[0] = F0;
+        F[1] = __builtin_fma(G, A.wn, p);
+        F[2] = G * A.wt1;
+        F[3] = G * A.wt2;
+        F[4] = (A.wn + A.wn) * __builtin_fma(4.0 * A.r, q, (gamma / (gamma - 1.0)) * p);
     }
 
     // Conserved-variable array of accumulator k in direction m's frame.
@@ -415,32 +511,30 @@ struct EulerFP32Split {
     using Node = EulerNodeF;
     static constexpr float kSqrtTau = 1e-6f;
 
-    // a1 in FP64, stored rounded to FP32; logs (hi, lo) of the stored values.
-    static constexpr int NREF = 4;  // rho_0, 1/rho_0, beta_0, 1/beta_0 (of the FP32-rounded values)
+    // a1 in FP64, stored rounded to FP32; logs (hi, lo) of the stored values
+    // against the element's first node (log_ratio).
+    static constexpr int NREF = 2;  // 1/rho_0, 1/beta_0 (of the FP32-rounded values)
     __device__ static void make_ref(const double *uc, double gamma, double *ref) {
-        double rf[4];
-        EulerFP64::make_ref(uc, gamma, rf);
-        ref[0] = (double)(float)rf[0];
-        ref[1] = rcp_fine(ref[0]);
-        ref[2] = (double)(float)rf[2];
-        ref[3] = rcp_fine(ref[2]);
+        double v[3], b;
+        EulerFP64::primitives(uc, gamma, v, b);
+        ref[0] = rcp_fine((double)(float)uc[0]);
+        ref[1] = rcp_fine((double)(float)b);
     }
 
     __device__ static void stage(const double *uc, const double *ref, double gamma, float *s) {
+        double v[3], b;
+        EulerFP64::primitives(uc, gamma, v, b);
         const double r = uc[0];
-        const double ir = rcp_fine(r);
-        const double v0 = uc[1] * ir, v1 = uc[2] * ir, v2 = uc[3] * ir;
-        const double p = (gamma - 1.0) * (uc[4] - 0.5 * r * (v0 * v0 + v1 * v1 + v2 * v2));
-        const double b = 0.5 * r * rcp_fine(p);
+        const double p = 0.5 * r * rcp_fine(b);
         const float rf = (float)r, bf = (float)b;
         s[S_R] = rf;
-        s[S_W + 0] = (float)(0.5 * v0);
-        s[S_W + 1] = (float)(0.5 * v1);
-        s[S_W + 2] = (float)(0.5 * v2);
+        s[S_W + 0] = (float)(0.5 * v[0]);
+        s[S_W + 1] = (float)(0.5 * v[1]);
+        s[S_W + 2] = (float)(0.5 * v[2]);
         s[S_B] = bf;
         s[S_P] = (float)p;
-        const double lr = log1p_series(((double)rf - ref[0]) * ref[1]);
-        const double lb = (0.5 / (gamma - 1.0)) * log1p_series(((double)bf - ref[2]) * ref[3]);
+        const double lr = log_ratio((double)rf, ref[0]);
+        const double lb = (0.5 / (gamma - 1.0)) * log_ratio((double)bf, ref[1]);
         const float lrh = (float)lr, lbh = (float)lb;
         s[S_LRH] = lrh;
         s[S_LRL] = (float)(lr - (double)lrh);
@@ -541,7 +635,7 @@ struct EulerCurvFP64 {
     static constexpr int NV = 5;
     static constexpr int NX = 9;   // Ja^m_k, m-major
     static constexpr int NS = 16;  // EulerFP64's 7 (unrotated) + 9 halved metric terms
-    static constexpr int NREF = 4;
+    static constexpr int NREF = EulerFP64::NREF;
     enum { S_R = 0, S_W = 1, S_B = 4, S_LR = 5, S_LB = 6, S_N = 7 };
     using Node = EulerCurvNode;
     using Consts = EulerFP64::Consts;
@@ -575,28 +669,9 @@ struct EulerCurvFP64 {
     __device__ static Consts consts(double cg) { return EulerFP64::consts(cg); }
 
     __device__ static void pair(const Node &A, const Node &C, const Consts &K, double *F) {
-        const double dr = A.r - C.r, sr = A.r + C.r;
-        const double db = A.b - C.b, sb = A.b + C.b;
-        double Nr = dr, Dr = A.lr - C.lr;
-        double Nb = db, Db = A.lb - C.lb;
-        if (__builtin_fabs(Dr) < K.thr_r) {  // near-equal densities: series
-            const double dr2 = dr * dr, sr2 = sr * sr;
-            const double u = dr2 * __builtin_amdgcn_rcp(sr2);
-            Nr = pin(0.5 * sr * sr2);
-            Dr = __builtin_fma(dr2, __builtin_fma(u, K.c5, K.c3), sr2);
-        }
-        if (__builtin_fabs(Db) < K.thr_b) {  // near-equal beta: series, times cg
-            const double db2 = db * db, sb2 = sb * sb;
-            const double u = db2 * __builtin_amdgcn_rcp(sb2);
-            Nb = pin(0.5 * sb * sb2);
-            Db = K.cg * __builtin_fma(db2, __builtin_fma(u, K.c5, K.c3), sb2);
-        }
-        const double DrNb = Dr * Nb;
-        const double R = rcp_fine(DrNb * sb);
-        const double rho_ln = Nr * (Nb * sb) * R;
-        const double cg_ibeta_ln = Db * (Dr * sb) * R;
-        const double phat = (0.5 * sr) * DrNb * R;
-
+        double rho_ln, cgib, phat;
+        EulerFP64::means(EulerNode{A.r, 0, 0, 0, A.b, A.lr, A.lb}, EulerNode{C.r, 0, 0, 0, C.b, C.lr, C.lb}, K,
+                         rho_ln, cgib, phat);
         const double v0 = A.w0 + C.w0, v1 = A.w1 + C.w1, v2 = A.w2 + C.w2;     // {{v}}
         const double n0 = A.n0 + C.n0, n1 = A.n1 + C.n1, n2 = A.n2 + C.n2;     // averaged Ja^m
         const double vn = __builtin_fma(v0, n0, __builtin_fma(v1, n1, v2 * n2));
@@ -606,22 +681,22 @@ struct EulerCurvFP64 {
         F[1] = __builtin_fma(F0, v0, phat * n0);
         F[2] = __builtin_fma(F0, v1, phat * n1);
         F[3] = __builtin_fma(F0, v2, phat * n2);
-        F[4] = __builtin_fma(F0, __builtin_fma(2.0, ww, cg_ibeta_ln), phat * vn);
+        F[4] = __builtin_fma(F0, __builtin_fma(2.0, ww, cgib), phat * vn);
     }
 
-    // physical flux f(u) . Ja^m at the node
+    // physical flux f(u) . Ja^m at the node (r = rho/2, w = v/2, halved metric)
     __device__ static void diag(const Node &A, double gamma, double *F) {
-        const double p = 0.5 * A.r * rcp_fine(A.b);
+        const double p = A.r * rcp_fine(A.b);
         const double v0 = A.w0 + A.w0, v1 = A.w1 + A.w1, v2 = A.w2 + A.w2;
         const double n0 = A.n0 + A.n0, n1 = A.n1 + A.n1, n2 = A.n2 + A.n2;
         const double vn = __builtin_fma(v0, n0, __builtin_fma(v1, n1, v2 * n2));
-        const double rvn = A.r * vn;
+        const double rvn = (A.r + A.r) * vn;
         const double q = __builtin_fma(v0, v0, __builtin_fma(v1, v1, v2 * v2));
         F[0] = rvn;
         F[1] = __builtin_fma(rvn, v0, p * n0);
         F[2] = __builtin_fma(rvn, v1, p * n1);
         F[3] = __builtin_fma(rvn, v2, p * n2);
-        F[4] = vn * __builtin_fma(gamma / (gamma - 1.0), p, 0.5 * A.r * q);
+        F[4] = vn * __builtin_fma(gamma / (gamma - 1.0), p, A.r * q);
     }
 
     __device__ static int out_array(int k, int) { return k; }

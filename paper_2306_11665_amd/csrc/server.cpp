@@ -122,7 +122,7 @@ public:
     virtual ~Executor() = default;
     virtual int init(size_t arena_bytes, int max_inflight) = 0;
     virtual char *arena_base() = 0;
-    virtual int mesh_upload(const double *u_host, size_t bytes, double **u_dev) = 0;
+    virtual int mesh_upload(const double *u_src, size_t bytes, double **u_dev) = 0;
     virtual void mesh_free(double *u_dev) = 0;
     // Launch a batch on slot s (asynchronous).
     virtual int launch(int s, const std::vector<ServeDesc> &descs) = 0;
@@ -182,12 +182,13 @@ public:
 
     char *arena_base() override { return reinterpret_cast<char *>(arena_); }
 
-    int mesh_upload(const double *u_host, size_t bytes, double **u_dev) override {
+    int mesh_upload(const double *u_src, size_t bytes, double **u_dev) override {
         if (hipMalloc(u_dev, bytes) != hipSuccess) {
             set_error("mesh allocation failed");
             return SF_ERR_NOMEM;
         }
-        if (hipMemcpy(*u_dev, u_host, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        // host or device source: the runtime tells them apart (unified addressing)
+        if (hipMemcpy(*u_dev, u_src, bytes, hipMemcpyDefault) != hipSuccess) {
             (void)hipFree(*u_dev);
             return fail_hip("mesh upload");
         }
@@ -377,8 +378,8 @@ public:
         for (auto &kv : meshes_) ex_->mesh_free(kv.second.u);
     }
 
-    int register_mesh(const double *u_host, int64_t E, int n, int flux, int node_kind, int64_t *out) {
-        if (!u_host || !out || E <= 0) return fail(SF_ERR_ARG, "null state or E <= 0");
+    int register_mesh(const double *u_src, int64_t E, int n, int flux, int node_kind, int64_t *out) {
+        if (!u_src || !out || E <= 0) return fail(SF_ERR_ARG, "null state or E <= 0");
         if (flux != SF_FLUX_EULER_CHANDRASHEKAR) return fail(SF_ERR_UNSUPPORTED, "serving is built for the Euler flux");
         if (node_kind != SF_NODES_GAUSS_LEGENDRE && node_kind != SF_NODES_GAUSS_LOBATTO)
             return fail(SF_ERR_ARG, "unknown node_kind");
@@ -389,7 +390,7 @@ public:
         m.n = n;
         m.node_kind = node_kind;
         m.out_bytes = align_up(bytes);
-        int st = ex_->mesh_upload(u_host, bytes, &m.u);
+        int st = ex_->mesh_upload(u_src, bytes, &m.u);
         if (st != SF_OK) return st;
         std::lock_guard<std::mutex> lk(mu_);
         *out = next_mesh_++;
@@ -488,6 +489,16 @@ public:
         if (used) *used = (int64_t)arena_.used();
     }
 
+    // batches launched, the most requests in one batch, the most launch
+    // slots running at once (continuous batching: > 1 means a batch started
+    // while another was still on the device)
+    void batch_stats(int64_t *batches, int64_t *max_reqs, int64_t *max_busy) {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (batches) *batches = batches_;
+        if (max_reqs) *max_reqs = max_batch_reqs_;
+        if (max_busy) *max_busy = max_slots_busy_;
+    }
+
 private:
     static int fail(int st, const char *msg) {
         set_error(msg);
@@ -537,6 +548,10 @@ private:
                 slot_reqs_[s].swap(pending_);
                 pending_.clear();
                 slot_busy_[s] = true;
+                batches_++;
+                max_batch_reqs_ = std::max(max_batch_reqs_, (int64_t)descs.size());
+                max_slots_busy_ = std::max(max_slots_busy_,
+                                           (int64_t)std::count(slot_busy_, slot_busy_ + kSlots, true));
                 lk.unlock();
                 int st = ex_->launch(s, descs);
                 lk.lock();
@@ -608,6 +623,7 @@ private:
     int launch_error_ = SF_OK;
     int64_t next_mesh_ = 1, next_ticket_ = 1;
     int inflight_ = 0;
+    int64_t batches_ = 0, max_batch_reqs_ = 0, max_slots_busy_ = 0;
     std::unordered_map<int64_t, Mesh> meshes_;
     std::unordered_map<int64_t, Request> reqs_;
     std::deque<int64_t> queue_;
@@ -659,10 +675,10 @@ int sf_server_create_sim(size_t hbm_budget_bytes, int max_inflight, double us_pe
     return create(std::make_unique<sfhad::serve::SimExecutor>(us_per_block), hbm_budget_bytes, max_inflight, out);
 }
 
-int sf_mesh_register(sf_server *srv, const double *u_host, int64_t E, int n, int flux_kind, int node_kind,
-                     sf_mesh *out) {
+int sf_mesh_register(sf_server *srv, const double *u_host_or_dev, int64_t E, int n, int flux_kind,
+                     int node_kind, sf_mesh *out) {
     if (!srv) return SF_ERR_ARG;
-    return srv->impl->register_mesh(u_host, E, n, flux_kind, node_kind, out);
+    return srv->impl->register_mesh(u_host_or_dev, E, n, flux_kind, node_kind, out);
 }
 
 int sf_submit(sf_server *srv, sf_mesh mesh, int precision, sf_ticket *out) {
@@ -693,6 +709,13 @@ int sf_mesh_unregister(sf_server *srv, sf_mesh mesh) {
 int sf_server_stats(sf_server *srv, int64_t *queued, int64_t *inflight, int64_t *budget_used) {
     if (!srv) return SF_ERR_ARG;
     srv->impl->stats(queued, inflight, budget_used);
+    return SF_OK;
+}
+
+int sf_server_batch_stats(sf_server *srv, int64_t *batches, int64_t *max_batch_requests,
+                          int64_t *max_slots_busy) {
+    if (!srv) return SF_ERR_ARG;
+    srv->impl->batch_stats(batches, max_batch_requests, max_slots_busy);
     return SF_OK;
 }
 

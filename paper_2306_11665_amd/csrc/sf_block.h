@@ -3,9 +3,12 @@
 // sf_block, which runs a block of elements through the steps below with a
 // per-line work policy (the volume pairs, the surface term, or both).
 //
-// One workgroup per block of EPB elements; d groups of LPD lanes, group m
-// handling every line of direction m of the block's elements, one line per
-// lane (at n = 8 in 3D: one element, 3 waves of 64 lanes, 64 lines each).
+// One workgroup per block of EPB elements, one line per lane.  Grouped
+// mapping (FE = 0): d groups of LPD lanes, group m handling every line of
+// direction m of the block's elements (at n = 8 in 3D: one element, 3 waves
+// of 64 lanes, 64 lines each).  Flat mapping (FE > 0 elements per block):
+// the lines of all directions laid out one after the other over the lanes,
+// the direction a per-lane value (Geom).
 //
 //   a1  stage:   coalesced SoA loads of the conserved state, conversion to
 //                the flux's per-node quantities, stored in LDS;
@@ -31,11 +34,12 @@ namespace dev {
 
 // a2..a5 for one line: every unordered pair (a < c) once plus the diagonal,
 // accumulated into t.  The loads of the stored arrays are rotated into the
-// frame of direction M.  With AHEAD (the standalone volume kernel at n <= 8,
-// where the registers allow it) the next partner's loads are issued before
-// the current pair's arithmetic, so their LDS latency overlaps it.
-template <int N, class P, int M, bool AHEAD, class Op>
-__device__ __forceinline__ void line_pairs(const typename P::Real *le, int AS, int pbase, int pstride,
+// frame of direction M (a constant after inlining in the grouped mapping, a
+// per-lane value in the flat one).  With AHEAD (the standalone volume kernel
+// where its launch shape asks for it) the next partner's loads are issued
+// before the current pair's arithmetic, so their LDS latency overlaps it.
+template <int N, class P, bool AHEAD, class Op>
+__device__ __forceinline__ void line_pairs(const int M, const typename P::Real *le, int AS, int pbase, int pstride,
                                            const Op &op, const typename P::Consts &K, double gamma,
                                            typename P::Real (&t)[N][P::NV]) {
     using R = typename P::Real;
@@ -94,9 +98,9 @@ constexpr int array_stride(int base) {
 // LDS needed by one block of the sum-factorized kernel: the staged inputs
 // (NS arrays of Real) and, after the compute phase, the FP64 outputs (NV
 // arrays of doubles, same stride) share the buffer.
-template <int N, int DIM, class P>
+template <int N, int DIM, class P, int FE = 0>
 struct SfLayout {
-    using G = Geom<N, DIM>;
+    using G = Geom<N, DIM, FE>;
     using R = typename P::Real;
     static constexpr int AS = array_stride<(int)sizeof(R)>(G::EPB * G::PADN);  // array distance (elements)
     static constexpr int IN_D = (P::NS * AS * (int)sizeof(R) + 7) / 8;
@@ -147,21 +151,27 @@ struct VolumeWorkT {
     __device__ __forceinline__ void lines(const R *le, int AS, int pbase, int pstride, const Op &op,
                                           const typename P::Consts &K, double gamma, R (&t)[N][P::NV], int64_t,
                                           int, double, const double *) const {
-        line_pairs<N, P, M, AHEAD && N <= 8>(le, AS, pbase, pstride, op, K, gamma, t);
+        line_pairs<N, P, AHEAD>(M, le, AS, pbase, pstride, op, K, gamma, t);
+    }
+    // the same with the direction a per-lane value (flat mapping)
+    template <int N, class P, class Op, class R>
+    __device__ __forceinline__ void lines_rt(int m, const R *le, int AS, int pbase, int pstride, const Op &op,
+                                             const typename P::Consts &K, double gamma, R (&t)[N][P::NV]) const {
+        line_pairs<N, P, AHEAD>(m, le, AS, pbase, pstride, op, K, gamma, t);
     }
 };
-using VolumeWork = VolumeWorkT<false>;       // serving and curvilinear kernels (register-capped)
-using VolumeWorkAhead = VolumeWorkT<true>;   // the standalone volume kernel
+using VolumeWork = VolumeWorkT<false>;  // serving and curvilinear kernels (register-capped)
 
 // One block of EPB elements starting at element e0 of an E-element mesh:
 // steps a1..a6 with the line work of `work`.  lds holds SfLayout::LDS_D
-// doubles, sref SfLayout::REF_D.
-template <int N, int DIM, class P, class Op, class Work = VolumeWork>
+// doubles, sref SfLayout::REF_D.  FE selects the lane mapping (Geom); the
+// flat mapping is built for the volume pairs only.
+template <int N, int DIM, class P, int FE = 0, class Op, class Work = VolumeWork>
 __device__ __forceinline__ void sf_block(const double *__restrict__ u, double *__restrict__ out, int64_t E,
                                          int64_t e0, const Op &op, double gamma, double *lds, double *sref,
                                          const Work &work = Work{}, const double *__restrict__ aux = nullptr) {
-    using G = Geom<N, DIM>;
-    using L = SfLayout<N, DIM, P>;
+    using G = Geom<N, DIM, FE>;
+    using L = SfLayout<N, DIM, P, FE>;
     using R = typename P::Real;
     constexpr int AS = L::AS;
     constexpr int NREF = L::NREF;
@@ -213,10 +223,8 @@ __device__ __forceinline__ void sf_block(const double *__restrict__ u, double *_
     __syncthreads();
 
     // a2..a5: one line per lane.
-    const int m = tid / G::LPD;
-    const int r = tid - m * G::LPD;
-    const int el = r / G::LINES;
-    const int line = r - el * G::LINES;
+    int el, m, line;
+    G::lane(tid, el, m, line);
     const bool active = el < nel;
     int pbase, pstride, q0, q1;
     line_geometry<N, DIM>(m, line, pbase, pstride, q0, q1);
@@ -230,7 +238,11 @@ __device__ __forceinline__ void sf_block(const double *__restrict__ u, double *_
 #pragma unroll
         for (int k = 0; k < P::NV; ++k) t[a][k] = (R)0;
 
-    if (active) {
+    if constexpr (FE > 0) {
+        // the direction varies across the wave: one instantiation with
+        // per-lane array offsets
+        if (active) work.template lines_rt<N, P>(m, le, AS, pbase, pstride, op, K, gamma, t);
+    } else if (active) {
         // m is uniform per wave; one instantiation per direction turns the
         // rotated array offsets into immediates
         const int64_t e = e0 + el;
@@ -248,7 +260,9 @@ __device__ __forceinline__ void sf_block(const double *__restrict__ u, double *_
     // reproducible): the first directions accumulate in LDS (the output
     // arrays reuse the input space), the last adds its own sums to the LDS
     // total and stores the result (for fixed a, the lanes of the last
-    // direction cover consecutive nodes: coalesced).
+    // direction cover consecutive nodes: coalesced).  In the flat mapping a
+    // wave may hold lanes of several directions; each lane takes part in
+    // the round of its own direction.
     double *lo = lout + el * G::PADN;
     const size_t obase = gbase + (size_t)el * G::NODES;
 #pragma unroll

@@ -69,7 +69,7 @@ struct SurfaceWork {
         }
         // the volume pairs last: staging a facet state (logarithms,
         // reciprocals) while their sums are live would spill at n = 8
-        if constexpr (VOLUME) line_pairs<NN, P, M, false>(le, AS, pbase, pstride, op, K, gamma, t);
+        if constexpr (VOLUME) line_pairs<NN, P, false>(M, le, AS, pbase, pstride, op, K, gamma, t);
     }
 };
 

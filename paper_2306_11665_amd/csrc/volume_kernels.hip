@@ -10,19 +10,30 @@
 namespace sfhad {
 namespace dev {
 
+// Launch shape of the standalone kernel: the 3D Euler flux takes
+// euler_volume_shape, the scalar fluxes the grouped mapping.
 template <int N, int DIM, class P>
-__global__ void __launch_bounds__((Geom<N, DIM>::THREADS))
+constexpr VolumeShape volume_shape() {
+    return (DIM == 3 && P::NV == 5) ? euler_volume_shape(N, sizeof(typename P::Real) == 8)
+                                    : VolumeShape{0, 1, N <= 8};
+}
+
+template <int N, int DIM, class P>
+__global__ void __launch_bounds__((Geom<N, DIM, volume_shape<N, DIM, P>().fe>::THREADS),
+                                  (volume_shape<N, DIM, P>().min_waves))
 sf_volume_kernel(const VolArgs<N> args) {
-    using L = SfLayout<N, DIM, P>;
+    constexpr int FE = volume_shape<N, DIM, P>().fe;
+    using L = SfLayout<N, DIM, P, FE>;
     __shared__ double lds[L::LDS_D];
     __shared__ double sref[L::REF_D];
-    const int64_t e0 = (int64_t)blockIdx.x * Geom<N, DIM>::EPB;
+    const int64_t e0 = (int64_t)blockIdx.x * Geom<N, DIM, FE>::EPB;
+    using Work = VolumeWorkT<volume_shape<N, DIM, P>().ahead>;
     if constexpr (N <= 9) {
-        sf_block<N, DIM, P>(args.u, args.out, args.E, e0, ParamOp<N>{args.op}, args.gamma, lds, sref,
-                            VolumeWorkAhead{});
+        sf_block<N, DIM, P, FE>(args.u, args.out, args.E, e0, ParamOp<N>{args.op}, args.gamma, lds, sref,
+                                Work{});
     } else {
         const auto A = kernel_args<VolArgs<N>>();
-        sf_block<N, DIM, P>(A->u, A->out, A->E, e0, KernargOp<N>{&A->op}, A->gamma, lds, sref, VolumeWorkAhead{});
+        sf_block<N, DIM, P, FE>(A->u, A->out, A->E, e0, KernargOp<N>{&A->op}, A->gamma, lds, sref, Work{});
     }
 }
 
@@ -40,7 +51,7 @@ VolArgs<N> make_args(const VolumeRequest &r) {
 
 template <int N, int DIM, class P>
 int launch_sf(const VolumeRequest &r) {
-    using G = Geom<N, DIM>;
+    using G = Geom<N, DIM, volume_shape<N, DIM, P>().fe>;
     const int64_t blocks = (r.E + G::EPB - 1) / G::EPB;
     if (blocks > 0x7fffffffLL) {
         set_error("element count too large for one launch");

@@ -38,6 +38,8 @@ def _lib():
         L.sf_server_create_sim.restype = ctypes.c_int
         L.sf_server_stats.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
         L.sf_server_stats.restype = ctypes.c_int
+        L.sf_server_batch_stats.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+        L.sf_server_batch_stats.restype = ctypes.c_int
         L._serving_ready = True
     return L
 
@@ -74,15 +76,24 @@ class Server:
         self.meshes: dict = {}
         self._tickets: dict = {}
 
-    def register(self, u_host: np.ndarray, n: int, nodes: str = "gl") -> MeshInfo:
-        u = np.ascontiguousarray(u_host, dtype=np.float64)
-        if u.ndim != 3 or u.shape[0] != 5 or u.shape[2] != n ** 3:
-            raise ValueError(f"state must be (5, E, {n ** 3}), got {u.shape}")
+    def register(self, u, n: int, nodes: str = "gl") -> MeshInfo:
+        """Register a mesh state (5, E, n^3): a host array, or a contiguous
+        float64 CUDA tensor (copied device to device)."""
+        if hasattr(u, "is_cuda") and u.is_cuda:
+            import torch
+            if u.dtype != torch.float64 or not u.is_contiguous():
+                raise ValueError("a device state must be a contiguous float64 tensor")
+            shape, ptr = tuple(u.shape), ctypes.cast(ctypes.c_void_p(u.data_ptr()), ctypes.POINTER(ctypes.c_double))
+            torch.cuda.synchronize(u.device)           # the state is complete before the copy
+        else:
+            u = np.ascontiguousarray(u, dtype=np.float64)
+            shape, ptr = u.shape, u.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if len(shape) != 3 or shape[0] != 5 or shape[2] != n ** 3:
+            raise ValueError(f"state must be (5, E, {n ** 3}), got {shape}")
         mid = _i64()
-        sfhad.check(_lib().sf_mesh_register(self._h, u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                            u.shape[1], n, sfhad.FLUX["euler"], sfhad.NODES[nodes],
+        sfhad.check(_lib().sf_mesh_register(self._h, ptr, shape[1], n, sfhad.FLUX["euler"], sfhad.NODES[nodes],
                                             ctypes.byref(mid)), "sf_mesh_register")
-        info = MeshInfo(mid.value, u.shape[1], n)
+        info = MeshInfo(mid.value, shape[1], n)
         self.meshes[info.mesh_id] = info
         return info
 
@@ -127,6 +138,13 @@ class Server:
         sfhad.check(_lib().sf_server_stats(self._h, ctypes.byref(q), ctypes.byref(i), ctypes.byref(u)),
                     "sf_server_stats")
         return q.value, i.value, u.value
+
+    def batch_stats(self):
+        """(batches launched, most requests in one batch, most slots busy at once)."""
+        b, r, k = _i64(), _i64(), _i64()
+        sfhad.check(_lib().sf_server_batch_stats(self._h, ctypes.byref(b), ctypes.byref(r), ctypes.byref(k)),
+                    "sf_server_batch_stats")
+        return b.value, r.value, k.value
 
     def close(self) -> None:
         if self._h:

@@ -135,6 +135,21 @@ def _stream_handle(stream) -> Optional[int]:
     return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
 
 
+def _record(stream, *tensors) -> None:
+    """Mark tensors as used on `stream` when it is not the current stream, so
+    that torch's caching allocator does not hand their memory to another
+    tensor while the launched kernels may still read or write it."""
+    import torch
+    if stream is None:
+        return
+    s = stream if isinstance(stream, torch.cuda.Stream) else torch.cuda.ExternalStream(int(stream))
+    if s.cuda_stream == torch.cuda.current_stream().cuda_stream:
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(s)
+
+
 def make_opts(nodes="gl", precision="fp64", gamma=1.4, stream=None, Q=None, w=None):
     o = SfOpts()
     lib().sf_opts_init(ctypes.byref(o))
@@ -187,6 +202,7 @@ def _call(fn_name: str, u, n: int, d: int, flux: str, *, nodes="gl", precision="
     fn = getattr(lib(), fn_name)
     check(fn(u.data_ptr(), u.shape[1], n, d, FLUX[flux], out.data_ptr(), ctypes.byref(opts)), fn_name)
     del keep
+    _record(stream, u, out)
     return out
 
 
@@ -218,6 +234,7 @@ def volume_curvilinear(u, Ja, n: int, flux: str = "euler", *, nodes="gl", gamma=
     check(lib().sf_hadamard_volume_curvilinear(u.data_ptr(), Ja.data_ptr(), E, n, FLUX[flux], out.data_ptr(),
                                                ctypes.byref(opts)), "sf_hadamard_volume_curvilinear")
     del keep
+    _record(stream, u, Ja, out)
     return out
 
 
@@ -232,6 +249,7 @@ def _entropy_map(name, x, gamma, stream, out):
         _check_out(out, x.shape, x)
     check(getattr(lib(), name)(x.data_ptr(), x.numel() // 5, out.data_ptr(), float(gamma), _stream_handle(stream)),
           name)
+    _record(stream, x, out)
     return out
 
 
@@ -258,6 +276,7 @@ def entropy_trace(u, n: int, *, nodes="gl", gamma=1.4, stream=None, out=None):
     opts, keep = make_opts(nodes, "fp64", gamma, stream)
     check(lib().sf_entropy_trace(u.data_ptr(), E, n, out.data_ptr(), ctypes.byref(opts)), "sf_entropy_trace")
     del keep
+    _record(stream, u, out)
     return out
 
 
@@ -295,6 +314,7 @@ def surface(u, uf, n: int, d: int, flux: str, *, with_volume=False, nodes="gl", 
     check(getattr(lib(), name)(u.data_ptr(), uf.data_ptr(), E, n, d, FLUX[flux], y_vol.data_ptr(),
                                y_face.data_ptr(), ctypes.byref(opts)), name)
     del keep
+    _record(stream, u, uf, y_vol, y_face)
     return y_vol, y_face
 
 
@@ -335,6 +355,7 @@ def tensor_apply(u, n: int, d: int, M, *, out=None, stream=None):
         raise ValueError(f"out must be a contiguous float64 tensor {shape} on u's device")
     check(lib().sf_tensor_apply_rect(u.data_ptr(), u.shape[1], n, n_out, d, u.shape[0], Mh.ctypes.data_as(_dp),
                                      out.data_ptr(), _stream_handle(stream)), "sf_tensor_apply_rect")
+    _record(stream, u, out)
     return out
 
 
@@ -346,6 +367,7 @@ def diag_log1p(x, stream=None):
     x = x.contiguous()
     y = torch.empty_like(x)
     check(lib().sf_diag_log1p(x.data_ptr(), x.numel(), y.data_ptr(), _stream_handle(stream)), "sf_diag_log1p")
+    _record(stream, x, y)
     return y
 
 

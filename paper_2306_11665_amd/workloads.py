@@ -95,6 +95,38 @@ def euler_state(E: int, n: int, seed: int, freestream_frac: float = 0.0, gamma: 
     return np.ascontiguousarray(primitives_to_conserved(rho, vel, p, gamma))
 
 
+def wide_ratio_euler_state(E: int, n: int, ratio: float, seed: int, rho_scale: float = 1.0,
+                           p_scale: float = 1.0, switch_tau: float = 0.0, vel_scale: float = 1.0,
+                           gamma: float = GAMMA) -> np.ndarray:
+    """Conserved Euler states (5, E, n^3) whose density and pressure vary
+    within each element by factors up to `ratio`: ln(rho / rho_scale) and
+    ln(p / p_scale) ~ U[-ln(ratio)/2, ln(ratio)/2] per node, velocity
+    components ~ vel_scale U[-0.5, 0.5] (a vel_scale of about
+    sqrt(p_scale / rho_scale) keeps the kinetic and internal energies of one
+    size, so that the pressure survives the conserved-variable round trip).  With switch_tau > 0, on every x-line the
+    second node is moved next to the first so that both |ln rho_1 - ln rho_0|
+    and |ln beta_1 - ln beta_0| (beta = rho / (2p)) equal switch_tau (1 + s)
+    with s drawn from {-1e-2, -1e-3, 1e-3, 1e-2} (signs random): node pairs
+    just either side of a log-difference threshold switch_tau."""
+    N = n ** 3
+    rng = np.random.default_rng(seed)
+    h = 0.5 * math.log(ratio)
+    lr = math.log(rho_scale) + rng.uniform(-h, h, size=(E, N))
+    lp = math.log(p_scale) + rng.uniform(-h, h, size=(E, N))
+    vel = vel_scale * rng.uniform(-0.5, 0.5, size=(3, E, N))
+    if switch_tau > 0.0:
+        first = np.arange(0, N, n)                     # node 0 of every x-line
+        k = first.size
+        s = np.array([-1e-2, -1e-3, 1e-3, 1e-2])
+        dr = switch_tau * (1 + rng.choice(s, size=(E, k))) * rng.choice([-1.0, 1.0], size=(E, k))
+        db = switch_tau * (1 + rng.choice(s, size=(E, k))) * rng.choice([-1.0, 1.0], size=(E, k))
+        lr[:, first + 1] = lr[:, first] + dr
+        # ln beta = ln rho - ln p - ln 2, so ln p moves by d(ln rho) - d(ln beta)
+        lp[:, first + 1] = lp[:, first] + dr - db
+    rho, p = np.exp(lr), np.exp(lp)
+    return np.ascontiguousarray(primitives_to_conserved(rho, vel, p, gamma))
+
+
 def _freestream_idx(E: int, n: int, seed: int, freestream_frac: float, d: int = 3) -> np.ndarray:
     N = n ** d
     rng = np.random.default_rng(seed)

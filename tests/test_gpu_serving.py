@@ -63,16 +63,39 @@ def test_alone_equals_mix(env):
             while time.perf_counter() - t0 < arr[k]:
                 pass
             tickets.append(srv.submit(meshes[which[k]].mesh_id, str(precs[k])))
-        max_q = 0
+        b0, _, _ = srv.batch_stats()
         for k, t in enumerate(tickets):
-            q, inflight, _ = srv.stats()
-            max_q = max(max_q, inflight)
             y = srv.result(t)
             ref = alone[(int(which[k]), str(precs[k]))]
             assert np.array_equal(y, ref), (k, int(which[k]), str(precs[k]))
             srv.release(t)
-        print("max requests holding memory at once:", max_q)
-        assert max_q > 1          # requests really overlapped
+        batches, max_reqs, max_busy = srv.batch_stats()
+        print(f"mix: {batches - b0} batches for {count} requests, at most {max_reqs} requests in one batch, "
+              f"at most {max_busy} batches on the device at once")
+        assert max_reqs >= 2      # requests that arrived while others ran were packed into one batch
+        assert max_busy >= 2      # a batch started while the previous one was still running
+
+
+def test_register_from_device_memory(env):
+    """sf_mesh_register takes a device pointer as well as a host one: both
+    registrations give the same, bitwise equal, results."""
+    torch, serving, sfhad, W = env
+    n, E = 5, 300
+    u = W.euler_state(E, n, seed=1350)
+    ud = torch.from_numpy(u).cuda()
+    with serving.Server(1 << 30, max_inflight=8) as srv:
+        mh = srv.register(u, n)
+        md = srv.register(ud, n)
+        del ud                                         # the server holds its own copy
+        torch.cuda.empty_cache()
+        out = []
+        for m in (mh, md):
+            t = srv.submit(m.mesh_id)
+            out.append(srv.result(t))
+            srv.release(t)
+        assert np.array_equal(out[0], out[1])
+        ref = sfhad.volume(torch.from_numpy(u).cuda(), n, 3, "euler").cpu().numpy()
+        assert np.array_equal(out[1], ref)
 
 
 def test_small_budget_forces_queueing(env):

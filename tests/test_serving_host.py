@@ -72,6 +72,8 @@ def test_requests_arriving_mid_flight_join_the_next_batch(serving):
         assert abs(l1 - l2) < 0.01
         assert l0 < la
         assert l1 > 0.13                   # 70 ms behind t0 and ta, then 80 ms of their own
+        # three batches (t0; ta; t1 + t2), two of them on the device at once
+        assert srv.batch_stats() == (3, 2, 2)
         for t in (t0, ta, t1, t2):
             srv.release(t)
 
