@@ -24,9 +24,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-FLUX = {"burgers": 0, "euler": 1, "product": 2}
+FLUX = {"burgers": 0, "euler": 1, "product": 2, "euler_pfix": 3}
 NODES = {"gl": 0, "gll": 1}
-NVAR = {"burgers": 1, "euler": 5, "product": 1}
+NVAR = {"burgers": 1, "euler": 5, "product": 1, "euler_pfix": 5}
 
 _lib = None
 

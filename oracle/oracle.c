@@ -80,7 +80,7 @@
 #include <omp.h>
 #endif
 
-enum { OR_FLUX_BURGERS = 0, OR_FLUX_EULER = 1, OR_FLUX_PRODUCT = 2 };
+enum { OR_FLUX_BURGERS = 0, OR_FLUX_EULER = 1, OR_FLUX_PRODUCT = 2, OR_FLUX_EULER_PFIX = 3 };
 enum { OR_NODES_GL = 0, OR_NODES_GLL = 1 };
 
 #define OR_PI 3.14159265358979323846264338327950288
@@ -244,6 +244,37 @@ void oracle_flux_euler(const double *uL, const double *uR, int m, double gamma, 
          + vbar[0] * F[1] + vbar[1] * F[2] + vbar[2] * F[3];
 }
 
+/* Chandrashekar's flux with Ranocha's pressure fix (the Results section
+ * names it, citing Ranocha & Gassner 2022, without printing it; reading:
+ * the arithmetic pressure mean {{p}} in the momentum flux, and the energy
+ * flux that Tadmor's entropy identity then requires, whose pressure work is
+ * (p_L v_mR + p_R v_mL)/2 -- parity unpinned by the paper):
+ *   F^rho    = rho^ln {{v_m}},
+ *   F^rhov_k = F^rho {{v_k}} + {{p}} delta_km,
+ *   F^E      = F^rho [ 1/(2 (gamma-1) beta^ln) + (v_L . v_R)/2 ]
+ *              + (p_L v_mR + p_R v_mL) / 2. */
+void oracle_flux_euler_pfix(const double *uL, const double *uR, int m, double gamma, double *F)
+{
+    double rl = uL[0], rr = uR[0];
+    double vl[3], vr[3], vbar[3];
+    for (int k = 0; k < 3; ++k) { vl[k] = uL[1 + k] / rl; vr[k] = uR[1 + k] / rr; }
+    double ql = vl[0] * vl[0] + vl[1] * vl[1] + vl[2] * vl[2];
+    double qr = vr[0] * vr[0] + vr[1] * vr[1] + vr[2] * vr[2];
+    double pl = (gamma - 1.0) * (uL[4] - 0.5 * rl * ql);
+    double pr = (gamma - 1.0) * (uR[4] - 0.5 * rr * qr);
+    double bl = rl / (2.0 * pl), br = rr / (2.0 * pr);
+
+    double rho_ln = oracle_logmean(rl, rr);
+    double beta_ln = oracle_logmean(bl, br);
+    double p_avg = 0.5 * (pl + pr);
+    double vlvr = vl[0] * vr[0] + vl[1] * vr[1] + vl[2] * vr[2];
+    for (int k = 0; k < 3; ++k) vbar[k] = 0.5 * (vl[k] + vr[k]);
+
+    F[0] = rho_ln * vbar[m];
+    for (int k = 0; k < 3; ++k) F[1 + k] = F[0] * vbar[k] + (k == m ? p_avg : 0.0);
+    F[4] = F[0] * (1.0 / (2.0 * (gamma - 1.0) * beta_ln) + 0.5 * vlvr) + 0.5 * (pl * vr[m] + pr * vl[m]);
+}
+
 /* Physical Euler flux f_m(u) (the consistency target f_m(u,u) = f_m(u)). */
 void oracle_physical_flux_euler(const double *u, int m, double gamma, double *F)
 {
@@ -255,12 +286,13 @@ void oracle_physical_flux_euler(const double *u, int m, double gamma, double *F)
     F[4] = (u[4] + p) * v[m];
 }
 
-static int flux_nvar(int flux) { return flux == OR_FLUX_EULER ? 5 : 1; }
+static int flux_nvar(int flux) { return (flux == OR_FLUX_EULER || flux == OR_FLUX_EULER_PFIX) ? 5 : 1; }
 
 /* f_m(u_L, u_R) for any supported flux; uL, uR point to nvar values. */
 void oracle_flux(int flux, const double *uL, const double *uR, int m, double gamma, double *F)
 {
     if (flux == OR_FLUX_EULER) oracle_flux_euler(uL, uR, m, gamma, F);
+    else if (flux == OR_FLUX_EULER_PFIX) oracle_flux_euler_pfix(uL, uR, m, gamma, F);
     else if (flux == OR_FLUX_BURGERS) F[0] = oracle_flux_burgers(uL[0], uR[0]);
     else F[0] = oracle_flux_product(uL[0], uR[0]);
 }

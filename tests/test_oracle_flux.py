@@ -131,3 +131,77 @@ def test_burgers_flux_pins(orc):
 
 def test_product_flux(orc):
     assert orc.flux("product", [3.0], [7.0], 1)[0] == 21.0
+
+
+# ------------------------------------------- pressure-fix variant (euler_pfix)
+# Chandrashekar's flux with Ranocha's pressure fix, which the Results section
+# names (citing Ranocha & Gassner 2022) without printing.  Reading: the
+# momentum flux carries the arithmetic pressure mean {{p}}; the energy flux is
+# then the one Tadmor's identity forces.  The pins below fix it without
+# retyping it: the pressure mean is computed here from the states, and the
+# energy flux is recovered from the entropy identity.
+
+def _pressure(u, g=GAMMA):
+    r = u[0]; v = u[1:4] / r
+    return (g - 1) * (u[4] - 0.5 * r * v @ v)
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_pfix_flux_symmetric_consistent_and_entropy_conservative(orc, m):
+    rng = np.random.default_rng(60 + m)
+    S = _rand_states(rng, 60)
+    for i in range(0, 60, 2):
+        uL, uR = S[i], S[i + 1]
+        F = orc.flux("euler_pfix", uL, uR, m, GAMMA)
+        np.testing.assert_allclose(F, orc.flux("euler_pfix", uR, uL, m, GAMMA), rtol=4e-16, atol=4e-16)
+        Fp = orc.physical_flux_euler(uL, m, GAMMA)
+        np.testing.assert_allclose(orc.flux("euler_pfix", uL, uL, m, GAMMA), Fp, rtol=0,
+                                   atol=8e-16 * max(1, np.abs(Fp).max()))
+        vL, psiL = _entropy_vars(uL); vR, psiR = _entropy_vars(uR)
+        assert abs((vR - vL) @ F - (psiR[m] - psiL[m])) < 1e-14
+
+
+def test_pfix_flux_momentum_and_energy_pinned(orc):
+    """Mass flux as Chandrashekar's, momentum flux F^rho {{v}} + {{p}} e_m with
+    the arithmetic pressure mean (computed here from the states), and the
+    energy flux equal to the unique solution of Tadmor's identity given
+    those; it differs from Chandrashekar's, whose pressure mean is
+    {{rho}}/(2 {{beta}})."""
+    rng = np.random.default_rng(70)
+    S = _rand_states(rng, 20)
+    for i in range(19):
+        uL, uR = S[i], S[i + 1]
+        vbar = 0.5 * (uL[1:4] / uL[0] + uR[1:4] / uR[0])
+        pavg = 0.5 * (_pressure(uL) + _pressure(uR))
+        vL, psiL = _entropy_vars(uL); vR, psiR = _entropy_vars(uR)
+        for m in range(3):
+            F = orc.flux("euler_pfix", uL, uR, m, GAMMA)
+            Fc = orc.flux("euler", uL, uR, m, GAMMA)
+            assert F[0] == pytest.approx(Fc[0], rel=1e-15)
+            for k in range(3):
+                want = F[0] * vbar[k] + (pavg if k == m else 0.0)
+                assert F[1 + k] == pytest.approx(want, rel=1e-14, abs=1e-15)
+            dv = vR - vL
+            FE = (psiR[m] - psiL[m] - dv[:4] @ F[:4]) / dv[4]
+            assert F[4] == pytest.approx(FE, rel=1e-11, abs=1e-13)
+            assert abs(F[1 + m] - Fc[1 + m]) > 1e-6       # a different pressure mean
+
+
+@pytest.mark.parametrize("flux", ["euler", "euler_pfix"])
+@pytest.mark.parametrize("n,kind", [(4, "gl"), (5, "gll")])
+def test_pressure_equilibrium_preserved(orc, flux, n, kind):
+    """Constant velocity and pressure with a varying density (a density wave):
+    y^(rho v) = v y^rho and y^E = |v|^2/2 y^rho at every node, so velocity
+    and pressure stay constant under the volume term (both fluxes)."""
+    from paper_2306_11665_amd import workloads as W
+    rng = np.random.default_rng(80 + n)
+    E, N = 3, n ** 3
+    rho = rng.uniform(0.5, 1.5, (E, N))
+    v = np.array([0.3, -0.2, 0.1])
+    vel = np.broadcast_to(v[:, None, None], (3, E, N))
+    u = np.ascontiguousarray(W.primitives_to_conserved(rho, vel, np.full((E, N), 0.8), GAMMA))
+    y = orc.dense_volume(u, n, 3, flux, nodes_kind=kind)
+    scale = np.abs(y).max()
+    for k in range(3):
+        assert np.abs(y[1 + k] - v[k] * y[0]).max() <= 1e-13 * scale
+    assert np.abs(y[4] - 0.5 * (v @ v) * y[0]).max() <= 1e-13 * scale

@@ -157,13 +157,14 @@ def test_burgers_linear_closed_form(orc, n, d, kind):
     assert np.abs(y[0, 0] - ref).max() < 2e-14 * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("flux", ["euler", "euler_pfix"])
 @pytest.mark.parametrize("n,kind", [(4, "gl"), (5, "gll"), (8, "gl")])
-def test_freestream_is_zero(orc, n, kind):
+def test_freestream_is_zero(orc, n, kind, flux):
     """Constant state: Q 1 = 0 and f(u,u) = f(u) give y = 0."""
     from paper_2306_11665_amd import workloads as W
     E = 2
     u = W.euler_state(E, n, seed=11, freestream_frac=1.0)
-    y = orc.dense_volume(u, n, 3, "euler", nodes_kind=kind)
+    y = orc.dense_volume(u, n, 3, flux, nodes_kind=kind)
     fmax = max(np.abs(orc.physical_flux_euler(u[:, e, 0], m)).max() for e in range(E) for m in range(3))
     assert np.abs(y).max() <= 1e-13 * fmax
 
@@ -235,11 +236,12 @@ def test_skew_part_sums_to_zero(orc):
 # ------------------------------------------------------ dense vs the method
 @pytest.mark.parametrize("flux,d,n,kind", [("burgers", 2, 4, "gll"), ("euler", 3, 4, "gl"),
                                           ("euler", 3, 5, "gll"), ("product", 3, 6, "gl"),
-                                          ("burgers", 3, 3, "gl"), ("euler", 3, 8, "gl")])
+                                          ("burgers", 3, 3, "gl"), ("euler", 3, 8, "gl"),
+                                          ("euler_pfix", 3, 5, "gl")])
 def test_sf_method_equals_dense_definition(orc, flux, d, n, kind):
     from paper_2306_11665_amd import workloads as W
     E = 2 if n >= 8 else 5
-    if flux == "euler":
+    if flux in ("euler", "euler_pfix"):
         u = W.euler_state(E, n, seed=3, d=d)
     else:
         u = W.scalar_state(E, n, d, seed=3)
