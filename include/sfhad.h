@@ -72,7 +72,15 @@ typedef enum {
 typedef enum {
     SF_FLUX_BURGERS_EC = 0,           /* f(a,b) = (a^2 + ab + b^2)/6, 1 variable */
     SF_FLUX_EULER_CHANDRASHEKAR = 1,  /* Chandrashekar's EC/KEP flux, 5 variables, d = 3 */
-    SF_FLUX_PRODUCT = 2               /* f(a,b) = a b (C_ij = c_i c_j of the Results section) */
+    SF_FLUX_PRODUCT = 2,              /* f(a,b) = a b (C_ij = c_i c_j of the Results section) */
+    SF_FLUX_EULER_CHANDRASHEKAR_PFIX = 3
+    /* Chandrashekar's flux with Ranocha's pressure fix (the flux of the
+     * Results section's Taylor-Green runs, cited there, not printed): the
+     * momentum flux takes the arithmetic pressure mean {{p}}, and the energy
+     * flux the entropy-conservative completion, whose pressure work is
+     * (p_L v_R + p_R v_L)/2.  5 variables, d = 3, FP64: the volume term, the
+     * dense path, the surface term and the curvilinear volume term (not the
+     * FP32-split form or the serving loop). */
 } sf_flux_kind;
 
 typedef enum {

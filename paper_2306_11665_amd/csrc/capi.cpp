@@ -47,12 +47,12 @@ int validate(const double *u, int64_t E, int n, int d, int flux, double *out, co
         return fail(SF_ERR_ARG, "op_1d_host and w_1d_host must be given together");
     if (d > 3 || d == 1) return fail(SF_ERR_UNSUPPORTED, "d must be 2 or 3");
     if (n < SF_MIN_N || n > SF_MAX_N) return fail(SF_ERR_UNSUPPORTED, "n outside [2, 16]");
-    if (flux == SF_FLUX_EULER_CHANDRASHEKAR) {
+    if (flux == SF_FLUX_EULER_CHANDRASHEKAR || flux == SF_FLUX_EULER_CHANDRASHEKAR_PFIX) {
         if (d != 3) return fail(SF_ERR_UNSUPPORTED, "the Euler flux is built for d = 3");
         if (n > SF_MAX_N_EULER) return fail(SF_ERR_UNSUPPORTED, "the Euler flux is built for n <= 13");
     }
     if (o.precision == SF_PREC_FP32_SPLIT && flux != SF_FLUX_EULER_CHANDRASHEKAR)
-        return fail(SF_ERR_UNSUPPORTED, "the FP32-split form is built for the Euler flux only");
+        return fail(SF_ERR_UNSUPPORTED, "the FP32-split form is built for the (plain) Euler flux only");
     if (dense) {
         if (ipow(n, d) > 4096) return fail(SF_ERR_UNSUPPORTED, "dense path needs n^d <= 4096");
         if (o.precision != SF_PREC_FP64) return fail(SF_ERR_UNSUPPORTED, "dense path is FP64 only");
@@ -128,7 +128,8 @@ int run_curvilinear(const double *u, const double *Ja, int64_t E, int n, int flu
     VolumeRequest r;
     int st = validate(u, E, n, 3, flux, out, opts, false, r);
     if (st != SF_OK) return st;
-    if (flux != SF_FLUX_EULER_CHANDRASHEKAR) return fail(SF_ERR_UNSUPPORTED, "the curvilinear term is built for the Euler flux");
+    if (flux != SF_FLUX_EULER_CHANDRASHEKAR && flux != SF_FLUX_EULER_CHANDRASHEKAR_PFIX)
+        return fail(SF_ERR_UNSUPPORTED, "the curvilinear term is built for the Euler fluxes");
     if (r.precision != SF_PREC_FP64) return fail(SF_ERR_UNSUPPORTED, "the curvilinear term is built in FP64 only");
     if (n > SF_MAX_N_CURV) return fail(SF_ERR_UNSUPPORTED, "the curvilinear term is built for n <= 10");
     if (E == 0) return SF_OK;

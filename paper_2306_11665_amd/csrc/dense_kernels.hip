@@ -158,6 +158,9 @@ int launch_dense_volume(const VolumeRequest &r) {
         case SF_FLUX_EULER_CHANDRASHEKAR:
             if (r.d != 3) break;
             return dispatch_dense_n<3, EulerFP64, SF_MAX_N_EULER>(r);
+        case SF_FLUX_EULER_CHANDRASHEKAR_PFIX:
+            if (r.d != 3) break;
+            return dispatch_dense_n<3, EulerPFixFP64, SF_MAX_N_EULER>(r);
         default: break;
     }
     set_error("flux / dimension combination not built");

@@ -318,46 +318,55 @@ struct ScalarFlux {
 // R = 1/(Dr Nb s_b): each quotient is its numerator times R times the other
 // two factors, formed as pairwise products.
 // Valid for rho, beta in about [1e-30, 1e30].
+//
+// PFIX: Chandrashekar's flux with Ranocha's pressure fix -- the momentum
+// flux takes the arithmetic pressure mean {{p}} instead of p_hat, and the
+// energy flux the entropy-conservative completion,
+//     F^E = F^rho [1/(2(gamma-1) beta^ln) + v_L.v_R/2] + (p_L v_nR + p_R v_nL)/2.
+// Half the pressure is stored as an eighth quantity (a sum of two is {{p}});
+// only rho^ln and cg/beta^ln are quotients, R = 1/(Dr Nb).
 // ---------------------------------------------------------------------------
 struct EulerNode {
-    double r, wn, wt1, wt2, b, lr, lb;
+    double r, wn, wt1, wt2, b, lr, lb, ph;
 };
 
-struct EulerFP64 {
+template <bool PFIX>
+struct EulerFP64T {
     using Real = double;
     static constexpr int NV = 5;
-    static constexpr int NS = 7;
+    static constexpr int NS = PFIX ? 8 : 7;
     static constexpr int NX = 0;
     static constexpr int NREF = 2;  // 1/rho_0, 1/beta_0
-    enum { S_R = 0, S_W = 1, S_B = 4, S_LR = 5, S_LB = 6 };
+    enum { S_R = 0, S_W = 1, S_B = 4, S_LR = 5, S_LB = 6, S_P = 7 };
     using Node = EulerNode;
     // Series branch when |ln a - ln b| < kLogTau, i.e. |a - b|/(a + b) =
     // tanh(|ln a - ln b| / 2) < ~1e-3 (u = f^2 < 1e-6).
     static constexpr double kLogTau = 2e-3;
 
-    // rho, beta = rho/(2p) of a conserved state; returns 1/rho, sets v
-    __device__ static double primitives(const double *uc, double gamma, double (&v)[3], double &beta) {
+    // v, p and beta = rho/(2p) of a conserved state; returns 1/rho
+    __device__ static double primitives(const double *uc, double gamma, double (&v)[3], double &p,
+                                        double &beta) {
         const double r = uc[0];
         const double ir = rcp_fine(r);
         v[0] = uc[1] * ir;
         v[1] = uc[2] * ir;
         v[2] = uc[3] * ir;
-        const double p = (gamma - 1.0) * (uc[4] - 0.5 * r * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+        p = (gamma - 1.0) * (uc[4] - 0.5 * r * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
         beta = 0.5 * r * rcp_fine(p);
         return ir;
     }
 
     // The element's reference values, from its first node's conserved state.
     __device__ static void make_ref(const double *uc, double gamma, double *ref) {
-        double v[3], b;
-        ref[0] = primitives(uc, gamma, v, b);
+        double v[3], p, b;
+        ref[0] = primitives(uc, gamma, v, p, b);
         ref[1] = rcp_fine(b);
     }
 
     // a1: conserved -> stored quantities (FP64, per node).
     __device__ static void stage(const double *uc, const double *ref, double gamma, double *s) {
-        double v[3], b;
-        primitives(uc, gamma, v, b);
+        double v[3], p, b;
+        primitives(uc, gamma, v, p, b);
         const double r = uc[0];
         s[S_R] = 0.5 * r;
         s[S_W + 0] = 0.5 * v[0];
@@ -366,6 +375,7 @@ struct EulerFP64 {
         s[S_B] = b;
         s[S_LR] = 0.5 * log_ratio(r, ref[0]);
         s[S_LB] = (0.5 / (gamma - 1.0)) * log_ratio(b, ref[1]);
+        if (PFIX) s[S_P] = 0.5 * p;
     }
 
     // Load node at padded index idx of one element's arrays (arrays are
@@ -381,6 +391,7 @@ struct EulerFP64 {
         A.b = lds[S_B * arrstride + idx];
         A.lr = lds[S_LR * arrstride + idx];
         A.lb = lds[S_LB * arrstride + idx];
+        A.ph = PFIX ? lds[S_P * arrstride + idx] : 0.0;
         return A;
     }
 
@@ -419,11 +430,18 @@ struct EulerFP64 {
             Nb = pin(0.5 * sb * sb2);
             Db = K.cg * __builtin_fma(db2, __builtin_fma(u, K.c5, K.c3), sb2);
         }
-        const double P1 = Nb * sb, P2 = Dr * sb, P3 = Dr * Nb;
-        const double R = rcp_fine(Dr * P1);
-        rho_ln = Nr * (P1 * R);
-        cgib = Db * (P2 * R);       // cg / beta^ln
-        phat = sr * (P3 * R);       // {{rho}} / (2 {{beta}})
+        if (PFIX) {  // no p_hat: R = 1/(Dr Nb)
+            const double R = rcp_fine(Dr * Nb);
+            rho_ln = Nr * (Nb * R);
+            cgib = Db * (Dr * R);
+            phat = 0.0;
+        } else {
+            const double P1 = Nb * sb, P2 = Dr * sb, P3 = Dr * Nb;
+            const double R = rcp_fine(Dr * P1);
+            rho_ln = Nr * (P1 * R);
+            cgib = Db * (P2 * R);       // cg / beta^ln
+            phat = sr * (P3 * R);       // {{rho}} / (2 {{beta}})
+        }
     }
 
     // a4: two-point flux f_n(A, C) in the line frame (cg is folded into lb).
@@ -434,18 +452,25 @@ struct EulerFP64 {
         const double ww = __builtin_fma(A.wn, C.wn, __builtin_fma(A.wt1, C.wt1, A.wt2 * C.wt2));  // v_L.v_R / 4
         const double F0 = rho_ln * vn;
         F[0] = F0;
-        F[1] = __builtin_fma(F0, vn, phat);
         F[2] = F0 * v1;
         F[3] = F0 * v2;
-        // F^E = F^rho [1/(2(gamma-1) beta^ln) + v_L.v_R/2] + p_hat {{v_n}}
-        F[4] = __builtin_fma(F0, __builtin_fma(2.0, ww, cgib), phat * vn);
+        if (PFIX) {
+            // {{p}} = ph_a + ph_c; (p_a v_nc + p_c v_na)/2 = 2 (ph_a w_nc + ph_c w_na)
+            const double work = __builtin_fma(A.ph, C.wn, C.ph * A.wn);
+            F[1] = __builtin_fma(F0, vn, A.ph + C.ph);
+            F[4] = __builtin_fma(F0, __builtin_fma(2.0, ww, cgib), work + work);
+        } else {
+            F[1] = __builtin_fma(F0, vn, phat);
+            // F^E = F^rho [1/(2(gamma-1) beta^ln) + v_L.v_R/2] + p_hat {{v_n}}
+            F[4] = __builtin_fma(F0, __builtin_fma(2.0, ww, cgib), phat * vn);
+        }
     }
 
     // Physical flux f_n(u) (the pair flux at equal states), from stored data
     // (r = rho/2, w = v/2): p = r/beta, rho v_n = 4 r w_n,
     // (E + p) v_n = 2 w_n (gamma/(gamma-1) p + 4 r |w|^2).
     __device__ static void diag(const Node &A, double gamma, double *F) {
-        const double p = A.r * rcp_fine(A.b);
+        const double p = PFIX ? A.ph + A.ph : A.r * rcp_fine(A.b);
         const double rw = A.r * A.wn;
         const double F0 = 4.0 * rw;
         const double G = 8.0 * rw;                       // rho v_n * 2
@@ -465,6 +490,8 @@ struct EulerFP64 {
         return 1 + comp;
     }
 };
+using EulerFP64 = EulerFP64T<false>;
+using EulerPFixFP64 = EulerFP64T<true>;
 
 // ---------------------------------------------------------------------------
 // FP32-split form of the Euler flux: stored quantities, pair and diagonal
@@ -515,17 +542,16 @@ struct EulerFP32Split {
     // against the element's first node (log_ratio).
     static constexpr int NREF = 2;  // 1/rho_0, 1/beta_0 (of the FP32-rounded values)
     __device__ static void make_ref(const double *uc, double gamma, double *ref) {
-        double v[3], b;
-        EulerFP64::primitives(uc, gamma, v, b);
+        double v[3], p, b;
+        EulerFP64::primitives(uc, gamma, v, p, b);
         ref[0] = rcp_fine((double)(float)uc[0]);
         ref[1] = rcp_fine((double)(float)b);
     }
 
     __device__ static void stage(const double *uc, const double *ref, double gamma, float *s) {
-        double v[3], b;
-        EulerFP64::primitives(uc, gamma, v, b);
+        double v[3], p, b;
+        EulerFP64::primitives(uc, gamma, v, p, b);
         const double r = uc[0];
-        const double p = 0.5 * r * rcp_fine(b);
         const float rf = (float)r, bf = (float)b;
         s[S_R] = rf;
         s[S_W + 0] = (float)(0.5 * v[0]);
@@ -624,28 +650,30 @@ struct EulerFP32Split {
 // pressure term p_hat n:
 //     F^rho = rho^ln {{v}}.n,  F^(rho v_k) = F^rho {{v_k}} + p_hat n_k,
 //     F^E = F^rho [1/(2(gamma-1) beta^ln) + v_L.v_R/2] + p_hat {{v}}.n .
+// With PFIX (the pressure fix) the pressure terms become {{p}} n_k and
+// (p_L v_R.n + p_R v_L.n)/2.
 // Velocities and results stay Cartesian (no rotation into a line frame).
 // ---------------------------------------------------------------------------
 struct EulerCurvNode {
-    double r, w0, w1, w2, b, lr, lb, n0, n1, n2;
+    double r, w0, w1, w2, b, lr, lb, ph, n0, n1, n2;
 };
 
-struct EulerCurvFP64 {
+template <bool PFIX>
+struct EulerCurvT {
+    using Base = EulerFP64T<PFIX>;
     using Real = double;
     static constexpr int NV = 5;
-    static constexpr int NX = 9;   // Ja^m_k, m-major
-    static constexpr int NS = 16;  // EulerFP64's 7 (unrotated) + 9 halved metric terms
-    static constexpr int NREF = EulerFP64::NREF;
-    enum { S_R = 0, S_W = 1, S_B = 4, S_LR = 5, S_LB = 6, S_N = 7 };
+    static constexpr int NX = 9;             // Ja^m_k, m-major
+    static constexpr int NS = Base::NS + 9;  // the Cartesian flux's stored values (unrotated) + 9 halved metric terms
+    static constexpr int NREF = Base::NREF;
+    enum { S_R = 0, S_W = 1, S_B = 4, S_LR = 5, S_LB = 6, S_P = 7, S_N = Base::NS };
     using Node = EulerCurvNode;
-    using Consts = EulerFP64::Consts;
+    using Consts = typename Base::Consts;
 
-    __device__ static void make_ref(const double *uc, double gamma, double *ref) {
-        EulerFP64::make_ref(uc, gamma, ref);
-    }
+    __device__ static void make_ref(const double *uc, double gamma, double *ref) { Base::make_ref(uc, gamma, ref); }
     // uc: the 5 conserved variables, then the 9 metric terms
     __device__ static void stage(const double *uc, const double *ref, double gamma, double *s) {
-        EulerFP64::stage(uc, ref, gamma, s);
+        Base::stage(uc, ref, gamma, s);
 #pragma unroll
         for (int j = 0; j < NX; ++j) s[S_N + j] = 0.5 * uc[NV + j];
     }
@@ -658,6 +686,7 @@ struct EulerCurvFP64 {
         A.b = lds[S_B * arrstride + idx];
         A.lr = lds[S_LR * arrstride + idx];
         A.lb = lds[S_LB * arrstride + idx];
+        A.ph = PFIX ? lds[S_P * arrstride + idx] : 0.0;
         A.n0 = lds[(S_N + 3 * m + 0) * arrstride + idx];
         A.n1 = lds[(S_N + 3 * m + 1) * arrstride + idx];
         A.n2 = lds[(S_N + 3 * m + 2) * arrstride + idx];
@@ -666,27 +695,40 @@ struct EulerCurvFP64 {
     __device__ static Node load_partner(const double *lds, int arrstride, int idx, int m) {
         return load(lds, arrstride, idx, m);
     }
-    __device__ static Consts consts(double cg) { return EulerFP64::consts(cg); }
+    __device__ static Consts consts(double cg) { return Base::consts(cg); }
 
     __device__ static void pair(const Node &A, const Node &C, const Consts &K, double *F) {
         double rho_ln, cgib, phat;
-        EulerFP64::means(EulerNode{A.r, 0, 0, 0, A.b, A.lr, A.lb}, EulerNode{C.r, 0, 0, 0, C.b, C.lr, C.lb}, K,
-                         rho_ln, cgib, phat);
+        Base::means(EulerNode{A.r, 0, 0, 0, A.b, A.lr, A.lb, 0}, EulerNode{C.r, 0, 0, 0, C.b, C.lr, C.lb, 0}, K,
+                    rho_ln, cgib, phat);
         const double v0 = A.w0 + C.w0, v1 = A.w1 + C.w1, v2 = A.w2 + C.w2;     // {{v}}
         const double n0 = A.n0 + C.n0, n1 = A.n1 + C.n1, n2 = A.n2 + C.n2;     // averaged Ja^m
         const double vn = __builtin_fma(v0, n0, __builtin_fma(v1, n1, v2 * n2));
         const double ww = __builtin_fma(A.w0, C.w0, __builtin_fma(A.w1, C.w1, A.w2 * C.w2));
         const double F0 = rho_ln * vn;
+        const double X = __builtin_fma(2.0, ww, cgib);
         F[0] = F0;
-        F[1] = __builtin_fma(F0, v0, phat * n0);
-        F[2] = __builtin_fma(F0, v1, phat * n1);
-        F[3] = __builtin_fma(F0, v2, phat * n2);
-        F[4] = __builtin_fma(F0, __builtin_fma(2.0, ww, cgib), phat * vn);
+        if (PFIX) {
+            // {{p}} = ph_a + ph_c; (p_a v_c.n + p_c v_a.n)/2 = 2 (ph_a w_c.n + ph_c w_a.n)
+            const double pavg = A.ph + C.ph;
+            const double wan = __builtin_fma(A.w0, n0, __builtin_fma(A.w1, n1, A.w2 * n2));
+            const double wcn = __builtin_fma(C.w0, n0, __builtin_fma(C.w1, n1, C.w2 * n2));
+            const double work = __builtin_fma(A.ph, wcn, C.ph * wan);
+            F[1] = __builtin_fma(F0, v0, pavg * n0);
+            F[2] = __builtin_fma(F0, v1, pavg * n1);
+            F[3] = __builtin_fma(F0, v2, pavg * n2);
+            F[4] = __builtin_fma(F0, X, work + work);
+        } else {
+            F[1] = __builtin_fma(F0, v0, phat * n0);
+            F[2] = __builtin_fma(F0, v1, phat * n1);
+            F[3] = __builtin_fma(F0, v2, phat * n2);
+            F[4] = __builtin_fma(F0, X, phat * vn);
+        }
     }
 
     // physical flux f(u) . Ja^m at the node (r = rho/2, w = v/2, halved metric)
     __device__ static void diag(const Node &A, double gamma, double *F) {
-        const double p = A.r * rcp_fine(A.b);
+        const double p = PFIX ? A.ph + A.ph : A.r * rcp_fine(A.b);
         const double v0 = A.w0 + A.w0, v1 = A.w1 + A.w1, v2 = A.w2 + A.w2;
         const double n0 = A.n0 + A.n0, n1 = A.n1 + A.n1, n2 = A.n2 + A.n2;
         const double vn = __builtin_fma(v0, n0, __builtin_fma(v1, n1, v2 * n2));
@@ -701,6 +743,8 @@ struct EulerCurvFP64 {
 
     __device__ static int out_array(int k, int) { return k; }
 };
+using EulerCurvFP64 = EulerCurvT<false>;
+using EulerCurvPFixFP64 = EulerCurvT<true>;
 
 }  // namespace dev
 }  // namespace sfhad

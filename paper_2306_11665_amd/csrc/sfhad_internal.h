@@ -97,6 +97,7 @@ inline int flux_nvar(int flux) {
         case SF_FLUX_BURGERS_EC: return 1;
         case SF_FLUX_PRODUCT: return 1;
         case SF_FLUX_EULER_CHANDRASHEKAR: return 5;
+        case SF_FLUX_EULER_CHANDRASHEKAR_PFIX: return 5;
         default: return 0;
     }
 }

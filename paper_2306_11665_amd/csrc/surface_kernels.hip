@@ -152,7 +152,8 @@ int dispatch_surface_n(const VolumeRequest &r) {
 
 // ---------------------------------------------------------------------------
 // Curvilinear elements: the volume kernel with the metric-averaged flux
-// (EulerCurvFP64); the 9 metric terms per node are staged with the state.
+// (EulerCurvFP64, or EulerCurvPFixFP64 with the pressure fix); the 9 metric
+// terms per node are staged with the state.
 template <int N>
 struct CurvArgs {
     const double *u;
@@ -163,15 +164,15 @@ struct CurvArgs {
     OpArg<N> op;
 };
 
-template <int N>
+template <int N, class P>
 __global__ void __launch_bounds__((Geom<N, 3>::THREADS))
 sf_curv_kernel(const CurvArgs<N>) {
-    using L = SfLayout<N, 3, EulerCurvFP64>;
+    using L = SfLayout<N, 3, P>;
     __shared__ double lds[L::LDS_D];
     __shared__ double sref[L::REF_D];
     const auto A = kernel_args<CurvArgs<N>>();
-    sf_block<N, 3, EulerCurvFP64>(A->u, A->out, A->E, (int64_t)blockIdx.x * Geom<N, 3>::EPB, KernargOp<N>{&A->op},
-                                  A->gamma, lds, sref, VolumeWork{}, A->Ja);
+    sf_block<N, 3, P>(A->u, A->out, A->E, (int64_t)blockIdx.x * Geom<N, 3>::EPB, KernargOp<N>{&A->op}, A->gamma,
+                      lds, sref, VolumeWork{}, A->Ja);
 }
 
 template <int N>
@@ -190,7 +191,12 @@ int launch_curv(const VolumeRequest &r) {
     a.gamma = r.gamma;
     for (int i = 0; i < N * N; ++i) a.op.Q[i] = r.op.Q[i];
     for (int i = 0; i < N; ++i) a.op.w[i] = r.op.w[i];
-    hipLaunchKernelGGL((sf_curv_kernel<N>), dim3((unsigned)blocks), dim3(G::THREADS), 0, r.stream, a);
+    if (r.flux == SF_FLUX_EULER_CHANDRASHEKAR_PFIX)
+        hipLaunchKernelGGL((sf_curv_kernel<N, EulerCurvPFixFP64>), dim3((unsigned)blocks), dim3(G::THREADS), 0,
+                           r.stream, a);
+    else
+        hipLaunchKernelGGL((sf_curv_kernel<N, EulerCurvFP64>), dim3((unsigned)blocks), dim3(G::THREADS), 0,
+                           r.stream, a);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) {
         set_error(std::string("sf_curv_kernel launch: ") + hipGetErrorString(err));
@@ -215,6 +221,9 @@ int launch_sf_surface(const VolumeRequest &r) {
         case SF_FLUX_EULER_CHANDRASHEKAR:
             if (r.d != 3) break;
             return dispatch_surface_n<3, EulerFP64, SF_MAX_N_EULER>(r);
+        case SF_FLUX_EULER_CHANDRASHEKAR_PFIX:
+            if (r.d != 3) break;
+            return dispatch_surface_n<3, EulerPFixFP64, SF_MAX_N_EULER>(r);
         default: break;
     }
     set_error("flux / dimension combination not built");

@@ -16,10 +16,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsfhad.so")
 
-FLUX = {"burgers": 0, "euler": 1, "product": 2}
+FLUX = {"burgers": 0, "euler": 1, "product": 2, "euler_pfix": 3}
 NODES = {"gl": 0, "gll": 1}
 PRECISION = {"fp64": 0, "fp32_split": 1}
-NVAR = {"burgers": 1, "euler": 5, "product": 1}
+NVAR = {"burgers": 1, "euler": 5, "product": 1, "euler_pfix": 5}
 STATUS = {0: "SF_OK", -1: "SF_ERR_ARG", -2: "SF_ERR_UNSUPPORTED", -3: "SF_ERR_HIP",
           -4: "SF_ERR_NOMEM", -5: "SF_ERR_BUDGET", -6: "SF_ERR_BUSY", -7: "SF_ERR_NOT_FOUND"}
 

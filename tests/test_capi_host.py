@@ -89,6 +89,10 @@ def test_validation_errors(sf, fn):
     assert f(BAD, 4, 4, 4, 0, BAD + 10 ** 9) == -2        # d = 4
     assert f(BAD, 4, 4, 2, 1, BAD + 10 ** 9) == -2        # Euler needs d = 3
     assert f(BAD, 4, 14, 3, 1, BAD + 10 ** 9) == -2       # Euler n <= 13
+    assert f(BAD, 4, 4, 2, 3, BAD + 10 ** 9) == -2        # the pressure-fix variant too
+    assert f(BAD, 4, 14, 3, 3, BAD + 10 ** 9) == -2
+    assert f(BAD, 4, 4, 3, 4, BAD + 10 ** 9) == -1        # no flux 4
+    assert f(None, 0, 4, 3, 3, None) == 0
     assert f(BAD, 4, 4, 3, 1, BAD) == -1                  # out aliases u
     assert f(BAD, 4, 4, 3, 1, BAD + 100) == -1            # out overlaps u
     assert f(None, 0, 4, 3, 1, None) == 0                 # E = 0: no-op
@@ -123,6 +127,7 @@ def test_opts_validation(sf):
     assert call(bad) == -1                                  # Q without w
     split = sf.SfOpts(); L.sf_opts_init(ctypes.byref(split)); split.precision = 1
     assert call(split, flux=0) == -2                        # FP32-split is Euler-only
+    assert call(split, flux=3) == -2                        # ... without the pressure fix
     assert call(split, fn="dense_hadamard_volume_ex") == -2  # dense is FP64-only
     # null opts means defaults; E = 0 is still a no-op
     assert L.sf_hadamard_volume_ex(None, 0, 4, 3, 1, None, None) == 0
