@@ -184,18 +184,9 @@ __device__ __forceinline__ void sf_block(const double *__restrict__ u, double *_
     const size_t vstride = (size_t)E * G::NODES;
     const size_t gbase = (size_t)e0 * G::NODES;
 
-    // a1: per-element reference values (from each element's first node), then
-    // stage the block's nodes.
-    if (P::NREF > 0) {
-        if (tid < nel) {
-            double uc[P::NV];
-#pragma unroll
-            for (int v = 0; v < P::NV; ++v) uc[v] = u[v * vstride + gbase + (size_t)tid * G::NODES];
-            P::make_ref(uc, gamma, sref + tid * NREF);
-        }
-        __syncthreads();
-    }
-    // every load of the staging pass is issued before any conversion
+    // a1: every load of the staging pass is issued before any conversion;
+    // the thread holding an element's first node then derives the element's
+    // reference values from it (one memory round trip for the whole stage)
     constexpr int SPT = (G::EPB * G::NODES + G::THREADS - 1) / G::THREADS;  // nodes per thread
     double uc[SPT][P::NV + P::NX];  // conserved variables, then P::NX extra inputs from aux
 #pragma unroll
@@ -207,6 +198,14 @@ __device__ __forceinline__ void sf_block(const double *__restrict__ u, double *_
 #pragma unroll
             for (int x = 0; x < P::NX; ++x) uc[k][P::NV + x] = aux[x * vstride + gbase + i];
         }
+    }
+    if (P::NREF > 0) {
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            const int i = tid + k * G::THREADS;
+            if (i < nvalid && i % G::NODES == 0) P::make_ref(uc[k], gamma, sref + (i / G::NODES) * NREF);
+        }
+        __syncthreads();
     }
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
