@@ -148,15 +148,37 @@ def serving_leg(torch, W, sfhad, n_req: int, fp64_dof_per_s: float) -> dict:
             if not rep:
                 log("[bench] serving: registered; timing each mesh alone")
         cap_alone = 1.0 / float(np.mean(svc))
+        # the mix's own kernel rate: every mesh through the standalone FP64
+        # kernel (HIP events), the same request mix with no serving overhead
+        kstream = torch.cuda.Stream()
+        kern = []
+        for s_ in specs:
+            us_ = torch.from_numpy(W.serving_mesh_state(s_)).cuda()
+            ys_ = torch.empty_like(us_)
+
+            def stepk():
+                sfhad.volume(us_, s_.n, 3, "euler", out=ys_, stream=kstream)
+
+            stepk()
+            kern.append(timed_launches(torch, stepk, 5, kstream)[1] * 1e-3)
+            del us_, ys_
+        cap_kernels = 1.0 / float(np.mean(kern))
+        dof_mean = float(np.mean([5 * s_.E * s_.n ** 3 for s_ in specs]))
         rng = np.random.default_rng(55)
         burst = rng.integers(0, len(meshes), size=max(64, n_req // 2))
         serving.saturation_rate(srv, meshes, burst)                       # warm
         cap = serving.saturation_rate(srv, meshes, burst)
         out["alone_ms_mean"] = float(np.mean(svc) * 1e3)
+        out["kernel_ms_mean"] = float(np.mean(kern) * 1e3)
+        out["alone_minus_kernel_ms_mean"] = float((np.mean(svc) - np.mean(kern)) * 1e3)
         out["capacity_alone_req_per_s"] = cap_alone
+        out["capacity_kernels_req_per_s"] = cap_kernels
         out["capacity_saturated_req_per_s"] = cap
-        log(f"[bench] serving: mean service time alone {np.mean(svc) * 1e3:.3f} ms ({cap_alone:.0f} req/s); "
-            f"saturated {cap:.0f} req/s")
+        out["saturated_frac_of_kernel_rate"] = cap / cap_kernels
+        out["kernel_rate_dof_per_s"] = cap_kernels * dof_mean
+        log(f"[bench] serving: mean service time alone {np.mean(svc) * 1e3:.3f} ms ({cap_alone:.0f} req/s), "
+            f"standalone kernels {np.mean(kern) * 1e3:.3f} ms ({cap_kernels:.0f} req/s); "
+            f"saturated {cap:.0f} req/s = {cap / cap_kernels:.2f} of the kernel rate")
         warm = max(20, n_req // 10)                                      # 200 at the default 2000
         runs = []
         for prec, frac in [("fp64", 0.5), ("fp64", 0.8), ("fp64", 0.95), ("fp32_split", 0.8), ("mixed", 0.8)]:
@@ -165,7 +187,8 @@ def serving_leg(torch, W, sfhad, n_req: int, fp64_dof_per_s: float) -> dict:
             res = serving.run_load(srv, meshes, arr, which, precision=precs, skip=warm)
             s = res.summary()
             s.update({"precision": prec, "offered_frac_of_saturated": frac, "offered_req_per_s": frac * cap,
-                      "dof_frac_of_single_request_fp64": s["dof_per_s"] / fp64_dof_per_s})
+                      "dof_frac_of_single_request_fp64": s["dof_per_s"] / fp64_dof_per_s,
+                      "dof_frac_of_mix_kernel_rate": s["dof_per_s"] / (cap_kernels * dof_mean)})
             runs.append(s)
             log(f"[bench] serving {prec} at {frac:.2f} C: p50 {s['p50_ms']:.3f} ms p99 {s['p99_ms']:.3f} ms "
                 f"{s['dof_per_s']:.3e} DOF/s (submit lateness max {s['max_submit_lateness_ms']:.2f} ms)")

@@ -9,13 +9,11 @@
 //    max_inflight requests hold output memory; a request larger than the
 //    whole budget is rejected at submission (SF_ERR_BUDGET).
 //  * Every scheduler tick packs all admitted, not yet launched requests into
-//    one launch: the per-(precision, n) persistent kernels of the batch are
-//    the nodes of a pre-built hipGraph (one graph per in-flight slot, two
-//    slots on two streams, so a new batch starts while the previous one
-//    drains); the batch's descriptors are copied from pinned memory, the
-//    nodes of variants the batch does not use are disabled and the others'
-//    grids set before the graph is replayed.  Requests that arrive while a
-//    batch runs go into the next one.
+//    one batch on a free launch slot (two slots on two streams, so a new
+//    batch starts while the previous one drains): one persistent kernel per
+//    (precision, n) variant present, its requests' descriptors in the kernel
+//    arguments (or, for large batches, copied once to the device).  Requests
+//    that arrive while a batch runs go into the next one.
 //  * Completion is observed by querying each slot's event; latency runs from
 //    sf_submit to that observation on the host's steady clock.  The output
 //    stays owned by the server until sf_release returns it to the budget.
@@ -35,6 +33,8 @@
 #include <thread>
 #include <unordered_map>
 #include <vector>
+
+#include <sys/prctl.h>
 
 #include "sfhad_internal.h"
 
@@ -136,14 +136,10 @@ class HipExecutor : public Executor {
 public:
     ~HipExecutor() override {
         for (int s = 0; s < kSlots; ++s) {
-            if (gexec_[s]) (void)hipGraphExecDestroy(gexec_[s]);
-            if (graph_[s]) (void)hipGraphDestroy(graph_[s]);
             if (ev_[s]) (void)hipEventDestroy(ev_[s]);
             if (st_[s]) (void)hipStreamDestroy(st_[s]);
             if (ddesc_[s]) (void)hipFree(ddesc_[s]);
-            if (dhdr_[s]) (void)hipFree(dhdr_[s]);
             if (hdesc_[s]) (void)hipHostFree(hdesc_[s]);
-            if (hhdr_[s]) (void)hipHostFree(hhdr_[s]);
         }
         if (optab_) (void)hipFree(optab_);
         if (arena_) (void)hipFree(arena_);
@@ -162,20 +158,12 @@ public:
         if (hipMemcpy(optab_, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
             return fail_hip("optable upload");
         const size_t dbytes = sizeof(ServeDesc) * (size_t)maxr_;
-        const size_t hbytes = sizeof(int) * 3 * kServeVariants;
         for (int s = 0; s < kSlots; ++s) {
             if (hipStreamCreateWithFlags(&st_[s], hipStreamNonBlocking) != hipSuccess) return fail_hip("stream");
             if (hipEventCreateWithFlags(&ev_[s], hipEventDisableTiming) != hipSuccess) return fail_hip("event");
-            if (hipMalloc(&ddesc_[s], dbytes) != hipSuccess || hipMalloc(&dhdr_[s], hbytes) != hipSuccess)
-                return fail_hip("descriptor buffers");
-            if (hipHostMalloc(&hdesc_[s], dbytes, hipHostMallocDefault) != hipSuccess ||
-                hipHostMalloc(&hhdr_[s], hbytes, hipHostMallocDefault) != hipSuccess)
-                return fail_hip("pinned descriptor buffers");
-            std::memset(hhdr_[s], 0, hbytes);
-            if (hipMemcpy(dhdr_[s], hhdr_[s], hbytes, hipMemcpyHostToDevice) != hipSuccess)
-                return fail_hip("descriptor header init");
-            int st = build_graph(s);
-            if (st != SF_OK) return st;
+            if (hipMalloc(&ddesc_[s], dbytes) != hipSuccess) return fail_hip("descriptor buffer");
+            if (hipHostMalloc(&hdesc_[s], dbytes, hipHostMallocDefault) != hipSuccess)
+                return fail_hip("pinned descriptor buffer");
         }
         return SF_OK;
     }
@@ -199,9 +187,14 @@ public:
         if (u_dev) (void)hipFree(u_dev);
     }
 
+    // One launch per (precision, n) variant of the batch, in order of
+    // decreasing work, on the slot's stream, then the slot's event.  A
+    // variant's descriptors (grouped, blk_begin counted per variant) go in
+    // the kernel arguments when there are at most kServeInline of them;
+    // otherwise the batch's descriptors are copied once to the slot's
+    // device array.  (A pre-built graph of all variants was measured first:
+    // its launch took about 0.26 ms of host time per batch.)
     int launch(int s, const std::vector<ServeDesc> &descs) override {
-        // descriptors grouped by variant, contiguous; header per variant:
-        // {count, total blocks, first descriptor}; blk_begin is per variant
         int count[kServeVariants] = {0};
         for (const ServeDesc &d : descs) count[serve_variant(d.n, d.prec)]++;
         int first[kServeVariants];
@@ -219,38 +212,39 @@ public:
             slot.blk_begin = total[v];
             total[v] += d.nblk;
         }
+        bool copy = false;
+        int order[kServeVariants];
+        int nv = 0;
         for (int v = 0; v < kServeVariants; ++v) {
             if (total[v] > 0x7fffffffLL) {
                 set_error("batch too large for one launch");
                 return SF_ERR_UNSUPPORTED;
             }
-            hhdr_[s][3 * v] = count[v];
-            hhdr_[s][3 * v + 1] = (int)total[v];
-            hhdr_[s][3 * v + 2] = first[v];
+            if (total[v] > 0) order[nv++] = v;
+            if (count[v] > kServeInline) copy = true;
         }
-        if (hipMemcpyAsync(ddesc_[s], hdesc_[s], sizeof(ServeDesc) * descs.size(), hipMemcpyHostToDevice,
-                           st_[s]) != hipSuccess ||
-            hipMemcpyAsync(dhdr_[s], hhdr_[s], sizeof(int) * 3 * kServeVariants, hipMemcpyHostToDevice,
-                           st_[s]) != hipSuccess)
+        std::sort(order, order + nv, [&](int a, int b) { return total[a] > total[b]; });
+        if (copy && hipMemcpyAsync(ddesc_[s], hdesc_[s], sizeof(ServeDesc) * descs.size(), hipMemcpyHostToDevice,
+                                   st_[s]) != hipSuccess)
             return fail_hip("descriptor copy");
-        for (int v = 0; v < kServeVariants; ++v) {
-            const bool on = total[v] > 0;
-            if (on != enabled_[s][v]) {
-                if (hipGraphNodeSetEnabled(gexec_[s], node_[s][v], on ? 1 : 0) != hipSuccess)
-                    return fail_hip("graph node enable");
-                enabled_[s][v] = on;
+        for (int k = 0; k < nv; ++k) {
+            const int v = order[k];
+            ServeArgs a;
+            a.optab = optab_;
+            a.ndesc = count[v];
+            a.total = (int32_t)total[v];
+            if (count[v] > kServeInline) {
+                a.desc = ddesc_[s] + first[v];
+            } else {
+                a.desc = nullptr;
+                std::memcpy(a.inl, hdesc_[s] + first[v], sizeof(ServeDesc) * count[v]);
             }
-            if (!on) continue;
+            void *kp[] = {&a};
             const int grid = (int)std::min<int64_t>(total[v], kGridCap);
-            if (grid != grid_[s][v]) {
-                hipKernelNodeParams p = params_[s][v];
-                p.gridDim = dim3(grid);
-                if (hipGraphExecKernelNodeSetParams(gexec_[s], node_[s][v], &p) != hipSuccess)
-                    return fail_hip("graph node update");
-                grid_[s][v] = grid;
-            }
+            if (hipLaunchKernel(serve_variant_kernel(v), dim3(grid), dim3(kServeThreads), kp, 0, st_[s]) !=
+                hipSuccess)
+                return fail_hip("serve kernel launch");
         }
-        if (hipGraphLaunch(gexec_[s], st_[s]) != hipSuccess) return fail_hip("hipGraphLaunch");
         if (hipEventRecord(ev_[s], st_[s]) != hipSuccess) return fail_hip("hipEventRecord");
         return SF_OK;
     }
@@ -264,53 +258,11 @@ private:
         return SF_ERR_HIP;
     }
 
-    int build_graph(int s) {
-        if (hipGraphCreate(&graph_[s], 0) != hipSuccess) return fail_hip("hipGraphCreate");
-        for (int v = 0; v < kServeVariants; ++v) {
-            args_[s][v].desc = ddesc_[s];
-            args_[s][v].hdr = dhdr_[s] + 3 * v;
-            args_[s][v].optab = optab_;
-            kargs_[s][v][0] = &args_[s][v].desc;
-            kargs_[s][v][1] = &args_[s][v].hdr;
-            kargs_[s][v][2] = &args_[s][v].optab;
-            hipKernelNodeParams &p = params_[s][v];
-            std::memset(&p, 0, sizeof(p));
-            p.func = const_cast<void *>(serve_variant_kernel(v));
-            p.gridDim = dim3(1);
-            p.blockDim = dim3(kServeThreads);
-            p.sharedMemBytes = 0;
-            p.kernelParams = kargs_[s][v];
-            p.extra = nullptr;
-            if (hipGraphAddKernelNode(&node_[s][v], graph_[s], nullptr, 0, &p) != hipSuccess)
-                return fail_hip("hipGraphAddKernelNode");
-            grid_[s][v] = 1;
-        }
-        if (hipGraphInstantiate(&gexec_[s], graph_[s], nullptr, nullptr, 0) != hipSuccess)
-            return fail_hip("hipGraphInstantiate");
-        for (int v = 0; v < kServeVariants; ++v) enabled_[s][v] = true;
-        return SF_OK;
-    }
-
-    struct Args {
-        const ServeDesc *desc;
-        const int *hdr;
-        const double *optab;
-    };
-
     int device_ = 0, maxr_ = 1;
     double *arena_ = nullptr, *optab_ = nullptr;
     hipStream_t st_[kSlots] = {};
     hipEvent_t ev_[kSlots] = {};
-    hipGraph_t graph_[kSlots] = {};
-    hipGraphExec_t gexec_[kSlots] = {};
-    hipGraphNode_t node_[kSlots][kServeVariants] = {};
-    hipKernelNodeParams params_[kSlots][kServeVariants];
-    Args args_[kSlots][kServeVariants];
-    void *kargs_[kSlots][kServeVariants][3];
-    int grid_[kSlots][kServeVariants];
-    bool enabled_[kSlots][kServeVariants];
     ServeDesc *ddesc_[kSlots] = {}, *hdesc_[kSlots] = {};
-    int *dhdr_[kSlots] = {}, *hhdr_[kSlots] = {};
 };
 
 // Host-only executor: a batch completes `us_per_block` microseconds per
@@ -594,6 +546,10 @@ private:
     }
 
     void loop() {
+        // the completion poll below sleeps a few microseconds; the default
+        // timer slack of a Linux thread (50 us) would stretch every such
+        // sleep to about 55 us, and with it every request's latency
+        (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
         std::unique_lock<std::mutex> lk(mu_);
         while (!stop_) {
             if (step(lk)) {

@@ -84,11 +84,21 @@ int64_t serve_blocks(int n, int64_t E);
 // Size in doubles of the operator table and its host-side filling.
 int serve_optable_doubles();
 void serve_fill_optable(double *host);
-// The persistent serving kernel of variant v = prec * 7 + (n - 2), with
-// arguments (const ServeDesc *desc, const int *hdr, const double *optable),
-// hdr = {ndesc, total_blocks, first descriptor} of that variant's requests.
+// The persistent serving kernel of variant v = prec * 7 + (n - 2); its only
+// argument is a ServeArgs, passed by value.
 constexpr int kServeVariants = 14;
 inline int serve_variant(int n, int prec) { return prec * (kServeMaxN - 1) + (n - 2); }
+// The requests of one variant's launch: their descriptors travel in the
+// kernel arguments when there are at most kServeInline of them (nothing to
+// copy before the launch), else in a device array.
+constexpr int kServeInline = 32;
+struct ServeArgs {
+    const ServeDesc *desc;  // device array of ndesc descriptors, or null: inl holds them
+    const double *optab;    // operator table (serve_fill_optable)
+    int32_t ndesc;          // requests of this launch
+    int32_t total;          // blocks of this launch (sum of nblk)
+    ServeDesc inl[kServeInline];
+};
 const void *serve_variant_kernel(int variant);
 
 // Number of conserved variables of a flux kind (0 for an unknown kind).

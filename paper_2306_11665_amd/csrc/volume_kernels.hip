@@ -101,24 +101,29 @@ __host__ __device__ constexpr int serve_table_off(int kind, int n) {
 
 template <int N, class P>
 __global__ void __launch_bounds__(kServeThreads, 3)
-serve_kernel(const ServeDesc *__restrict__ desc, const int *__restrict__ hdr, const double *__restrict__ optab) {
+serve_kernel(const ServeArgs) {
     static_assert(Geom<N, 3>::THREADS == kServeThreads, "serving assumes 192-thread blocks");
     using L = SfLayout<N, 3, P>;
     __shared__ double lds[L::LDS_D];
     __shared__ double sref[L::REF_D];
-    const int ndesc = hdr[0];
-    const int total = hdr[1];
-    desc += hdr[2];
+    const auto A = kernel_args<ServeArgs>();
+    // the descriptors: a device array, or the argument block itself (the
+    // kernel-argument segment is ordinary readable memory); global address
+    // space, so that the uniform reads stay scalar loads
+    using GDesc = const __attribute__((address_space(1))) ServeDesc;
+    GDesc *__restrict__ dd = A->desc ? (GDesc *)A->desc : (GDesc *)&A->inl[0];
+    const int ndesc = A->ndesc;
+    const int total = A->total;
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         int lo = 0, hi = ndesc - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (desc[mid].blk_begin <= b) lo = mid; else hi = mid - 1;
+            if (dd[mid].blk_begin <= b) lo = mid; else hi = mid - 1;
         }
         lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: keep the descriptor scalar
-        const ServeDesc D = desc[lo];
+        GDesc &D = dd[lo];
         const int off = __builtin_amdgcn_readfirstlane(serve_table_off(D.node_kind, N));
-        const TableOp op{optab + off, optab + off + N * N};
+        const TableOp op{A->optab + off, A->optab + off + N * N};
         // gamma is uniform per descriptor: keep it (and the flux constants
         // derived from it) in scalar registers
         const int64_t gbits = __builtin_bit_cast(int64_t, D.gamma);
