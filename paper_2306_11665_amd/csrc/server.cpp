@@ -11,9 +11,11 @@
 //  * Every scheduler tick packs all admitted, not yet launched requests into
 //    one batch on a free launch slot (two slots on two streams, so a new
 //    batch starts while the previous one drains): one persistent kernel per
-//    (precision, n) variant present, its requests' descriptors in the kernel
-//    arguments (or, for large batches, copied once to the device).  Requests
-//    that arrive while a batch runs go into the next one.
+//    (precision, n) variant present, each a pre-built one-node hipGraph
+//    replayed with the batch's grid and arguments -- its requests'
+//    descriptors in the kernel arguments (or, for large batches, copied once
+//    to the device).  Requests that arrive while a batch runs go into the
+//    next one.
 //  * Completion is observed by querying each slot's event; latency runs from
 //    sf_submit to that observation on the host's steady clock.  The output
 //    stays owned by the server until sf_release returns it to the budget.
@@ -136,6 +138,10 @@ class HipExecutor : public Executor {
 public:
     ~HipExecutor() override {
         for (int s = 0; s < kSlots; ++s) {
+            for (int v = 0; v < kServeVariants; ++v) {
+                if (gexec_[s][v]) (void)hipGraphExecDestroy(gexec_[s][v]);
+                if (graph_[s][v]) (void)hipGraphDestroy(graph_[s][v]);
+            }
             if (ev_[s]) (void)hipEventDestroy(ev_[s]);
             if (st_[s]) (void)hipStreamDestroy(st_[s]);
             if (ddesc_[s]) (void)hipFree(ddesc_[s]);
@@ -164,6 +170,10 @@ public:
             if (hipMalloc(&ddesc_[s], dbytes) != hipSuccess) return fail_hip("descriptor buffer");
             if (hipHostMalloc(&hdesc_[s], dbytes, hipHostMallocDefault) != hipSuccess)
                 return fail_hip("pinned descriptor buffer");
+            for (int v = 0; v < kServeVariants; ++v) {
+                int st = build_graph(s, v);
+                if (st != SF_OK) return st;
+            }
         }
         return SF_OK;
     }
@@ -188,12 +198,14 @@ public:
     }
 
     // One launch per (precision, n) variant of the batch, in order of
-    // decreasing work, on the slot's stream, then the slot's event.  A
-    // variant's descriptors (grouped, blk_begin counted per variant) go in
-    // the kernel arguments when there are at most kServeInline of them;
-    // otherwise the batch's descriptors are copied once to the slot's
-    // device array.  (A pre-built graph of all variants was measured first:
-    // its launch took about 0.26 ms of host time per batch.)
+    // decreasing work, on the slot's stream, then the slot's event.  Each
+    // (slot, variant) owns a one-node graph of its persistent kernel; a
+    // launch sets the node's grid and arguments and replays it.  A variant's
+    // descriptors (grouped, blk_begin counted per variant) go in the kernel
+    // arguments when there are at most kServeInline of them; otherwise the
+    // batch's descriptors are copied once to the slot's device array.  (One
+    // graph holding all 14 variants, with the unused nodes disabled per
+    // batch, took about 0.26 ms of host time per launch.)
     int launch(int s, const std::vector<ServeDesc> &descs) override {
         int count[kServeVariants] = {0};
         for (const ServeDesc &d : descs) count[serve_variant(d.n, d.prec)]++;
@@ -229,7 +241,7 @@ public:
             return fail_hip("descriptor copy");
         for (int k = 0; k < nv; ++k) {
             const int v = order[k];
-            ServeArgs a;
+            ServeArgs &a = args_[s][v];
             a.optab = optab_;
             a.ndesc = count[v];
             a.total = (int32_t)total[v];
@@ -239,11 +251,11 @@ public:
                 a.desc = nullptr;
                 std::memcpy(a.inl, hdesc_[s] + first[v], sizeof(ServeDesc) * count[v]);
             }
-            void *kp[] = {&a};
-            const int grid = (int)std::min<int64_t>(total[v], kGridCap);
-            if (hipLaunchKernel(serve_variant_kernel(v), dim3(grid), dim3(kServeThreads), kp, 0, st_[s]) !=
-                hipSuccess)
-                return fail_hip("serve kernel launch");
+            hipKernelNodeParams p = params_[s][v];
+            p.gridDim = dim3((unsigned)std::min<int64_t>(total[v], kGridCap));
+            if (hipGraphExecKernelNodeSetParams(gexec_[s][v], node_[s][v], &p) != hipSuccess)
+                return fail_hip("graph node update");
+            if (hipGraphLaunch(gexec_[s][v], st_[s]) != hipSuccess) return fail_hip("hipGraphLaunch");
         }
         if (hipEventRecord(ev_[s], st_[s]) != hipSuccess) return fail_hip("hipEventRecord");
         return SF_OK;
@@ -258,11 +270,36 @@ private:
         return SF_ERR_HIP;
     }
 
+    int build_graph(int s, int v) {
+        if (hipGraphCreate(&graph_[s][v], 0) != hipSuccess) return fail_hip("hipGraphCreate");
+        std::memset(&args_[s][v], 0, sizeof(ServeArgs));
+        kargs_[s][v][0] = &args_[s][v];
+        hipKernelNodeParams &p = params_[s][v];
+        std::memset(&p, 0, sizeof(p));
+        p.func = const_cast<void *>(serve_variant_kernel(v));
+        p.gridDim = dim3(1);
+        p.blockDim = dim3(serve_threads(v));
+        p.sharedMemBytes = 0;
+        p.kernelParams = kargs_[s][v];
+        p.extra = nullptr;
+        if (hipGraphAddKernelNode(&node_[s][v], graph_[s][v], nullptr, 0, &p) != hipSuccess)
+            return fail_hip("hipGraphAddKernelNode");
+        if (hipGraphInstantiate(&gexec_[s][v], graph_[s][v], nullptr, nullptr, 0) != hipSuccess)
+            return fail_hip("hipGraphInstantiate");
+        return SF_OK;
+    }
+
     int device_ = 0, maxr_ = 1;
     double *arena_ = nullptr, *optab_ = nullptr;
     hipStream_t st_[kSlots] = {};
     hipEvent_t ev_[kSlots] = {};
     ServeDesc *ddesc_[kSlots] = {}, *hdesc_[kSlots] = {};
+    hipGraph_t graph_[kSlots][kServeVariants] = {};
+    hipGraphExec_t gexec_[kSlots][kServeVariants] = {};
+    hipGraphNode_t node_[kSlots][kServeVariants] = {};
+    hipKernelNodeParams params_[kSlots][kServeVariants];
+    ServeArgs args_[kSlots][kServeVariants];
+    void *kargs_[kSlots][kServeVariants][1];
 };
 
 // Host-only executor: a batch completes `us_per_block` microseconds per
@@ -492,7 +529,7 @@ private:
                     d.n = m.n;
                     d.prec = r.prec;
                     d.node_kind = m.node_kind;
-                    d.nblk = (int32_t)serve_blocks(m.n, m.E);
+                    d.nblk = (int32_t)serve_blocks(m.n, r.prec, m.E);
                     d.gamma = 1.4;
                     descs.push_back(d);
                     r.state = State::Running;

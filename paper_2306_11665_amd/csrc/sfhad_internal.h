@@ -76,11 +76,10 @@ struct ServeDesc {
     double gamma;
 };
 constexpr int kServeMaxN = 8;
-constexpr int kServeThreads = 192;
 
 // Blocks (workgroups' work units) a request of E elements with n nodes per
-// direction takes: ceil(E / elements-per-block(n)).
-int64_t serve_blocks(int n, int64_t E);
+// direction takes in precision prec: ceil(E / elements-per-block).
+int64_t serve_blocks(int n, int prec, int64_t E);
 // Size in doubles of the operator table and its host-side filling.
 int serve_optable_doubles();
 void serve_fill_optable(double *host);
@@ -100,6 +99,8 @@ struct ServeArgs {
     ServeDesc inl[kServeInline];
 };
 const void *serve_variant_kernel(int variant);
+// Threads per block of that kernel (its lane mapping's block size).
+int serve_threads(int variant);
 
 // Number of conserved variables of a flux kind (0 for an unknown kind).
 inline int flux_nvar(int flux) {

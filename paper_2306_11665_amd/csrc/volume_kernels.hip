@@ -99,11 +99,19 @@ __host__ __device__ constexpr int serve_table_off(int kind, int n) {
     return kind * kServeKindDoubles + serve_table_size(n - 1);
 }
 
+// The serving kernels take the standalone kernel's lane mapping (flat where
+// it fills more lanes), at least 3 waves per SIMD, no look-ahead load (the
+// persistent loop's state leaves no registers for it).
 template <int N, class P>
-__global__ void __launch_bounds__(kServeThreads, 3)
+constexpr int serve_fe() {
+    return euler_volume_shape(N, sizeof(typename P::Real) == 8).fe;
+}
+
+template <int N, class P>
+__global__ void __launch_bounds__((Geom<N, 3, serve_fe<N, P>()>::THREADS), 3)
 serve_kernel(const ServeArgs) {
-    static_assert(Geom<N, 3>::THREADS == kServeThreads, "serving assumes 192-thread blocks");
-    using L = SfLayout<N, 3, P>;
+    constexpr int FE = serve_fe<N, P>();
+    using L = SfLayout<N, 3, P, FE>;
     __shared__ double lds[L::LDS_D];
     __shared__ double sref[L::REF_D];
     const auto A = kernel_args<ServeArgs>();
@@ -130,26 +138,51 @@ serve_kernel(const ServeArgs) {
         const int glo = __builtin_amdgcn_readfirstlane((int)(gbits & 0xffffffff));
         const int ghi = __builtin_amdgcn_readfirstlane((int)(gbits >> 32));
         const double gamma = __builtin_bit_cast(double, ((int64_t)ghi << 32) | (uint32_t)glo);
-        sf_block<N, 3, P>(D.u, D.out, D.E, (b - D.blk_begin) * Geom<N, 3>::EPB, op, gamma, lds, sref);
+        sf_block<N, 3, P, FE>(D.u, D.out, D.E, (b - D.blk_begin) * Geom<N, 3, FE>::EPB, op, gamma, lds, sref);
         __syncthreads();  // the next block reuses the LDS
     }
 }
 
 }  // namespace dev
 
-int64_t serve_blocks(int n, int64_t E) {
-    int epb = 1;
-    switch (n) {
-        case 2: epb = dev::Geom<2, 3>::EPB; break;
-        case 3: epb = dev::Geom<3, 3>::EPB; break;
-        case 4: epb = dev::Geom<4, 3>::EPB; break;
-        case 5: epb = dev::Geom<5, 3>::EPB; break;
-        case 6: epb = dev::Geom<6, 3>::EPB; break;
-        case 7: epb = dev::Geom<7, 3>::EPB; break;
-        case 8: epb = dev::Geom<8, 3>::EPB; break;
-        default: return -1;
+namespace {
+template <int N>
+void serve_geom(int prec, int &epb, int &threads) {
+    if (prec == SF_PREC_FP32_SPLIT) {
+        using G = dev::Geom<N, 3, dev::serve_fe<N, dev::EulerFP32Split>()>;
+        epb = G::EPB;
+        threads = G::THREADS;
+    } else {
+        using G = dev::Geom<N, 3, dev::serve_fe<N, dev::EulerFP64>()>;
+        epb = G::EPB;
+        threads = G::THREADS;
     }
+}
+
+bool serve_geom(int n, int prec, int &epb, int &threads) {
+    switch (n) {
+        case 2: serve_geom<2>(prec, epb, threads); return true;
+        case 3: serve_geom<3>(prec, epb, threads); return true;
+        case 4: serve_geom<4>(prec, epb, threads); return true;
+        case 5: serve_geom<5>(prec, epb, threads); return true;
+        case 6: serve_geom<6>(prec, epb, threads); return true;
+        case 7: serve_geom<7>(prec, epb, threads); return true;
+        case 8: serve_geom<8>(prec, epb, threads); return true;
+        default: return false;
+    }
+}
+}  // namespace
+
+int64_t serve_blocks(int n, int prec, int64_t E) {
+    int epb, threads;
+    if (!serve_geom(n, prec, epb, threads)) return -1;
     return (E + epb - 1) / epb;
+}
+
+int serve_threads(int variant) {
+    int epb = 1, threads = 0;
+    serve_geom(variant % (kServeMaxN - 1) + 2, variant / (kServeMaxN - 1), epb, threads);
+    return threads;
 }
 
 int serve_optable_doubles() { return 2 * dev::kServeKindDoubles; }
