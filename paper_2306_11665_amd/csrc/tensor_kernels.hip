@@ -225,12 +225,34 @@ __device__ __forceinline__ int qdiv(int x, uint32_t rc) { return (int)__umulhi((
 // index products: every factor is below 2^16, so the full-rate 24-bit multiply is exact
 __device__ __forceinline__ int m24(int a, int b) { return __mul24(a, b); }
 
-template <int DIM>
+__host__ __device__ constexpr uint32_t rect_rc(int64_t d) {
+    return (uint32_t)(((int64_t)1 << 32) / d + ((((int64_t)1 << 32) % d) != 0));
+}
+__host__ __device__ constexpr int rect_pow(int b, int e) { return e == 0 ? 1 : b * rect_pow(b, e - 1); }
+// slabs per block: the LDS stage holds kRectStage doubles, and the lines of
+// a pass fill at most 4 waves x kRectTPW tiles of 16
+__host__ __device__ constexpr int rect_slabs_per_block(int ni, int no, int d) {
+    const int mx = ni > no ? ni : no;
+    const int mxd = rect_pow(mx, d), mxl = rect_pow(mx, d - 1);
+    const int g1 = kRectStage / mxd, g2 = 64 * kRectTPW / mxl;
+    const int g = g1 < g2 ? g1 : g2;
+    return g < 1 ? 1 : g;
+}
+
+// NI, NO > 0: the sizes as compile-time constants (every index split and
+// product folds into shifts and constant multiplies); 0: run-time sizes
+// from the arguments.  The code is the same.
+template <int DIM, int NI, int NO>
 __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectArgs) {
     extern __shared__ double buf[];
     const auto A = kernel_args<RectArgs>();
-    const int ni = A->ni, no = A->no, G = A->G, cap = A->cap;
-    const uint32_t rc_ni = A->rc_ni, rc_no = A->rc_no;
+    constexpr bool CT = NI > 0 && NO > 0;
+    constexpr int MX = NI > NO ? NI : NO;
+    const int ni = CT ? NI : A->ni, no = CT ? NO : A->no;
+    const int G = CT ? rect_slabs_per_block(NI, NO, DIM) : A->G;
+    const int cap = CT ? rect_pow(MX, DIM) + rect_pow(MX, DIM - 1) : A->cap;
+    const uint32_t rc_ni = CT ? rect_rc(NI) : A->rc_ni, rc_no = CT ? rect_rc(NO) : A->rc_no;
+    const uint32_t rc_nin = CT ? rect_rc(rect_pow(NI, DIM)) : A->rc_nin;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int nin = 1, nout = 1;
 #pragma unroll
@@ -255,7 +277,7 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
     for (int j = 0; j < SPT; ++j) {
         const int i = tid + j * kTensorThreads;
         if (i < total) {
-            const int g = qdiv(i, A->rc_nin), lin = i - m24(g, nin);
+            const int g = qdiv(i, rc_nin), lin = i - m24(g, nin);
             buf[m24(g, cap) + lin + qdiv(lin, rc_ni)] = v[j];
         }
     }
@@ -306,7 +328,15 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
             if (t >= tiles) continue;
             const int Lg = t * 16 + (lane & 15);
             ok[u] = Lg < nlines;
-            const int g = ok[u] ? qdiv(Lg, A->rc_lps[m]) : 0;
+            uint32_t rc_lps = A->rc_lps[m];
+            if (CT) {
+                int lp = 1;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k)
+                    if (k != m) lp *= k < m ? NO : NI;
+                rc_lps = rect_rc(lp);
+            }
+            const int g = ok[u] ? qdiv(Lg, rc_lps) : 0;
             int L = ok[u] ? Lg - m24(g, lps) : 0;
             // coordinates of the other directions, increasing order, first fastest
             int c[3] = {0, 0, 0};
@@ -363,49 +393,47 @@ int launch_tensor_apply(const TensorRequest &r) {
 
 int launch_tensor_rect(const TensorRequest &r) {
     using namespace dev;
-    const int mx = r.n > r.n_out ? r.n : r.n_out;
-    int mxd = 1, mxl = 1;
-    for (int k = 0; k < r.d; ++k) mxd *= mx;
-    mxl = mxd / mx;
-    // slabs per block: the LDS stage holds kRectStage doubles, and the
-    // lines of a pass fill at most 4 waves x kRectTPW tiles of 16
-    int G = kRectStage / mxd;
-    if (64 * kRectTPW / mxl < G) G = 64 * kRectTPW / mxl;
-    if (G < 1) G = 1;
     RectArgs a;
     a.in = r.in;
     a.out = r.out;
     a.slabs = r.E * r.nvar;
     a.ni = r.n;
     a.no = r.n_out;
-    a.G = G;
-    a.cap = mxd + mxl;
-    auto rc = [](int64_t d) { return (uint32_t)(((int64_t)1 << 32) / d + ((((int64_t)1 << 32) % d) != 0)); };
-    int nin = 1;
-    for (int k = 0; k < r.d; ++k) nin *= r.n;
-    a.rc_ni = rc(r.n);
-    a.rc_no = rc(r.n_out);
-    a.rc_nin = rc(nin);
+    a.G = rect_slabs_per_block(r.n, r.n_out, r.d);
+    const int mx = r.n > r.n_out ? r.n : r.n_out;
+    a.cap = rect_pow(mx, r.d) + rect_pow(mx, r.d - 1);
+    a.rc_ni = rect_rc(r.n);
+    a.rc_no = rect_rc(r.n_out);
+    a.rc_nin = rect_rc(rect_pow(r.n, r.d));
     for (int m = 0; m < 3; ++m) {
         int lps = 1;
         for (int k = 0; k < r.d; ++k)
             if (k != m) lps *= k < m ? r.n_out : r.n;
-        a.rc_lps[m] = m < r.d ? rc(lps) : 0;
+        a.rc_lps[m] = m < r.d ? rect_rc(lps) : 0;
     }
     for (int i = 0; i < r.n_out * r.n; ++i) a.M[i] = r.M[i];
-    const int64_t blocks = (a.slabs + G - 1) / G;
+    const int64_t blocks = (a.slabs + a.G - 1) / a.G;
     if (blocks > 0x7fffffffLL) {
         set_error("too many elements for one launch");
         return SF_ERR_UNSUPPORTED;
     }
-    const size_t lds = sizeof(double) * (size_t)G * a.cap;
-    if (r.d == 2)
-        hipLaunchKernelGGL(tensor_rect_kernel<2>, dim3((unsigned)blocks), dim3(kTensorThreads), lds, r.stream, a);
-    else
-        hipLaunchKernelGGL(tensor_rect_kernel<3>, dim3((unsigned)blocks), dim3(kTensorThreads), lds, r.stream, a);
-    const hipError_t err = hipGetLastError();
-    if (err != hipSuccess) {
-        set_error(std::string("tensor_rect_kernel launch: ") + hipGetErrorString(err));
+    const size_t lds = sizeof(double) * (size_t)a.G * a.cap;
+    // compile-time sizes for the over-integration pairs of the modal path
+    // (n modes <-> n + 2 quadrature nodes, n = 3..8, 3D); run-time otherwise
+    const void *fn = nullptr;
+    if (r.d == 3) {
+#define SF_RECT(NI_, NO_) \
+        if (r.n == NI_ && r.n_out == NO_) fn = reinterpret_cast<const void *>(&tensor_rect_kernel<3, NI_, NO_>);
+        SF_RECT(3, 5) SF_RECT(5, 3) SF_RECT(4, 6) SF_RECT(6, 4) SF_RECT(5, 7) SF_RECT(7, 5)
+        SF_RECT(6, 8) SF_RECT(8, 6) SF_RECT(7, 9) SF_RECT(9, 7) SF_RECT(8, 10) SF_RECT(10, 8)
+#undef SF_RECT
+        if (!fn) fn = reinterpret_cast<const void *>(&tensor_rect_kernel<3, 0, 0>);
+    } else {
+        fn = reinterpret_cast<const void *>(&tensor_rect_kernel<2, 0, 0>);
+    }
+    void *kp[] = {&a};
+    if (hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(kTensorThreads), kp, lds, r.stream) != hipSuccess) {
+        set_error(std::string("tensor_rect_kernel launch: ") + hipGetErrorString(hipGetLastError()));
         return SF_ERR_HIP;
     }
     return SF_OK;
