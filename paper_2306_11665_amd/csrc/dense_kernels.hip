@@ -102,8 +102,7 @@ VolArgs<N> make_dense_args(const VolumeRequest &r) {
     a.out = r.out;
     a.E = r.E;
     a.gamma = r.gamma;
-    for (int i = 0; i < N * N; ++i) a.op.Q[i] = r.op.Q[i];
-    for (int i = 0; i < N; ++i) a.op.w[i] = r.op.w[i];
+    fill_op_arg<N>(a.op, r.op);
     return a;
 }
 

@@ -29,7 +29,18 @@ template <int N>
 struct OpArg {
     double Q[N * N];
     double w[N];
+    float Qf[N * N];  // Q rounded to FP32, for the FP32-split form's line sums
 };
+
+// Fill an OpArg from a host operator (op.Q, op.w of n = N).
+template <int N, class Op1D>
+void fill_op_arg(OpArg<N> &a, const Op1D &op) {
+    for (int i = 0; i < N * N; ++i) {
+        a.Q[i] = op.Q[i];
+        a.Qf[i] = (float)op.Q[i];
+    }
+    for (int i = 0; i < N; ++i) a.w[i] = op.w[i];
+}
 
 // The whole argument block of a standalone volume kernel, its only
 // parameter.  Kernels read it through the kernel-argument segment pointer
@@ -501,9 +512,9 @@ using EulerPFixFP64 = EulerFP64T<true>;
 // kept as two FP32 words (hi + lo), so ln a - ln b of two close states keeps
 // ~1e-16 absolute accuracy and the direct form
 // (a - b)/(ln a - ln b) stays accurate to FP32 rounding until a and b are
-// within about 1e-6 relative.  Below that (u = ((a-b)/(a+b))^2 < 1e-12, tested
-// in FP32, exact equality included) the logarithmic mean is evaluated in FP64
-// by the series and rounded.
+// within about 1e-6 relative.  Below that (|ln a - ln b| < 2e-6, tested on
+// the hi + lo differences, exact equality included) the logarithmic mean is
+// evaluated in FP64 by the series and rounded.
 // ---------------------------------------------------------------------------
 struct EulerNodeF {
     float r, wn, wt1, wt2, b, p, lrh, lrl, lbh, lbl;
@@ -536,30 +547,31 @@ struct EulerFP32Split {
     static constexpr int NX = 0;
     enum { S_R = 0, S_W = 1, S_B = 4, S_P = 5, S_LRH = 6, S_LRL = 7, S_LBH = 8, S_LBL = 9 };
     using Node = EulerNodeF;
-    static constexpr float kSqrtTau = 1e-6f;
+    // FP64 series below |ln a - ln b| = 2e-6, i.e. |a - b| < ~1e-6 (a + b)
+    static constexpr float kLogTau = 2e-6f;
 
-    // a1 in FP64, stored rounded to FP32; logs (hi, lo) of the stored values
-    // against the element's first node (log_ratio).
+    // a1 in FP64, stored rounded to FP32 in the FP64 form's halved layout
+    // (r = rho/2, w = v/2, lr = ln(rho/rho_0)/2 as hi + lo); the logarithms
+    // are of the stored values, against the element's first node (log_ratio).
     static constexpr int NREF = 2;  // 1/rho_0, 1/beta_0 (of the FP32-rounded values)
     __device__ static void make_ref(const double *uc, double gamma, double *ref) {
         double v[3], p, b;
         EulerFP64::primitives(uc, gamma, v, p, b);
-        ref[0] = rcp_fine((double)(float)uc[0]);
+        ref[0] = rcp_fine((double)(float)(0.5 * uc[0]));
         ref[1] = rcp_fine((double)(float)b);
     }
 
     __device__ static void stage(const double *uc, const double *ref, double gamma, float *s) {
         double v[3], p, b;
         EulerFP64::primitives(uc, gamma, v, p, b);
-        const double r = uc[0];
-        const float rf = (float)r, bf = (float)b;
+        const float rf = (float)(0.5 * uc[0]), bf = (float)b;
         s[S_R] = rf;
         s[S_W + 0] = (float)(0.5 * v[0]);
         s[S_W + 1] = (float)(0.5 * v[1]);
         s[S_W + 2] = (float)(0.5 * v[2]);
         s[S_B] = bf;
         s[S_P] = (float)p;
-        const double lr = log_ratio((double)rf, ref[0]);
+        const double lr = 0.5 * log_ratio((double)rf, ref[0]);
         const double lb = (0.5 / (gamma - 1.0)) * log_ratio((double)bf, ref[1]);
         const float lrh = (float)lr, lbh = (float)lb;
         s[S_LRH] = lrh;
@@ -591,29 +603,33 @@ struct EulerFP32Split {
     }
 
     struct Consts {
-        float cg;
+        float cg, thr_r, thr_b;
     };
-    __device__ static Consts consts(double cg) { return Consts{(float)cg}; }
+    __device__ static Consts consts(double cg) {
+        return Consts{(float)cg, 0.5f * kLogTau, (float)(kLogTau * cg)};
+    }
 
+    // As the FP64 form, in FP32 (halved density and logarithm, one
+    // reciprocal for the three quotients); the switch to the FP64 series is
+    // tested on the (hi + lo) logarithm differences.
     __device__ static void pair(const Node &A, const Node &C, const Consts &K, float *F) {
-        const float cg = K.cg;
-        const float dr = A.r - C.r, sr = A.r + C.r;
+        const float dr = A.r - C.r, sr = A.r + C.r;   // (rho_a - rho_c)/2, {{rho}}
         const float db = A.b - C.b, sb = A.b + C.b;
         float Nr = dr, Dr = pin((A.lrh - C.lrh) + (A.lrl - C.lrl));
         float Nb = db, Db = pin((A.lbh - C.lbh) + (A.lbl - C.lbl));
-        if (__builtin_fabsf(dr) < kSqrtTau * sr) {  // near-identical densities: FP64 series
-            Nr = (float)logmean_near64(A.r, C.r);
-            Dr = 1.0f;
+        if (__builtin_fabsf(Dr) < K.thr_r) {  // near-identical densities: FP64 series of the halves,
+            Nr = (float)logmean_near64(A.r, C.r);  // rho^ln / 2, over a halved log difference of 1/2
+            Dr = 0.5f;
         }
-        if (__builtin_fabsf(db) < kSqrtTau * sb) {  // near-identical beta: FP64 series
-            Db = (float)((double)cg * inv_logmean_near64(A.b, C.b));
+        if (__builtin_fabsf(Db) < K.thr_b) {  // near-identical beta: FP64 series
+            Db = (float)((double)K.cg * inv_logmean_near64(A.b, C.b));
             Nb = 1.0f;
         }
-        const float DrNb = Dr * Nb;
-        const float R = rcpf(DrNb * sb);
-        const float rho_ln = Nr * (Nb * sb) * R;
-        const float cg_ibeta_ln = Db * (Dr * sb) * R;
-        const float phat = (0.5f * sr) * DrNb * R;
+        const float P1 = Nb * sb, P2 = Dr * sb, P3 = Dr * Nb;
+        const float R = rcpf(Dr * P1);
+        const float rho_ln = Nr * (P1 * R);
+        const float cgib = Db * (P2 * R);
+        const float phat = sr * (P3 * R);
 
         const float vn = A.wn + C.wn, v1 = A.wt1 + C.wt1, v2 = A.wt2 + C.wt2;
         const float ww = __builtin_fmaf(A.wn, C.wn, __builtin_fmaf(A.wt1, C.wt1, A.wt2 * C.wt2));
@@ -622,18 +638,20 @@ struct EulerFP32Split {
         F[1] = __builtin_fmaf(F0, vn, phat);
         F[2] = F0 * v1;
         F[3] = F0 * v2;
-        F[4] = __builtin_fmaf(F0, __builtin_fmaf(2.0f, ww, cg_ibeta_ln), phat * vn);
+        F[4] = __builtin_fmaf(F0, __builtin_fmaf(2.0f, ww, cgib), phat * vn);
     }
 
+    // physical flux from the stored halves: rho v_n = 4 r w_n,
+    // (E + p) v_n = 2 w_n (gamma/(gamma-1) p + 4 r |w|^2)
     __device__ static void diag(const Node &A, double gamma, float *F) {
-        const float vn = A.wn + A.wn, v1 = A.wt1 + A.wt1, v2 = A.wt2 + A.wt2;
-        const float rvn = A.r * vn;
-        const float q = __builtin_fmaf(vn, vn, __builtin_fmaf(v1, v1, v2 * v2));
-        F[0] = rvn;
-        F[1] = __builtin_fmaf(rvn, vn, A.p);
-        F[2] = rvn * v1;
-        F[3] = rvn * v2;
-        F[4] = vn * __builtin_fmaf((float)(gamma / (gamma - 1.0)), A.p, 0.5f * A.r * q);
+        const float rw = A.r * A.wn;
+        const float G = 8.0f * rw;
+        const float q = __builtin_fmaf(A.wn, A.wn, __builtin_fmaf(A.wt1, A.wt1, A.wt2 * A.wt2));
+        F[0] = 4.0f * rw;
+        F[1] = __builtin_fmaf(G, A.wn, A.p);
+        F[2] = G * A.wt1;
+        F[3] = G * A.wt2;
+        F[4] = (A.wn + A.wn) * __builtin_fmaf(4.0f * A.r, q, (float)(gamma / (gamma - 1.0)) * A.p);
     }
 
     __device__ static int out_array(int k, int m) { return EulerFP64::out_array(k, m); }

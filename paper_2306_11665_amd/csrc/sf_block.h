@@ -32,6 +32,16 @@
 namespace sfhad {
 namespace dev {
 
+// Q[i] in the line sums' type (the FP32 copy for FP32 sums: a scalar load,
+// no per-lane conversion).
+template <class R, class Op>
+__device__ __forceinline__ R op_q(const Op &op, int i) {
+    if constexpr (sizeof(R) == 4)
+        return op.qf(i);
+    else
+        return op.q(i);
+}
+
 // a2..a5 for one line: every unordered pair (a < c) once plus the diagonal,
 // accumulated into t.  The loads of the stored arrays are rotated into the
 // frame of direction M (a constant after inlining in the grouped mapping, a
@@ -56,7 +66,7 @@ __device__ __forceinline__ void line_pairs(const int M, const typename P::Real *
         const Node A = P::load(at(a), AS, 0, M);
         R F[P::NV];
         P::diag(A, gamma, F);
-        const R qaa = (R)op.q(a * N + a);
+        const R qaa = op_q<R>(op, a * N + a);
 #pragma unroll
         for (int k = 0; k < P::NV; ++k) t[a][k] = qaa * F[k] + t[a][k];
         Node C;
@@ -67,7 +77,7 @@ __device__ __forceinline__ void line_pairs(const int M, const typename P::Real *
             if (!AHEAD) C = P::load_partner(at(c), AS, 0, M);
             else if (c + 1 < N) Cn = P::load_partner(at(c + 1), AS, 0, M);
             P::pair(A, C, K, F);
-            const R qac = (R)op.q(a * N + c), qca = (R)op.q(c * N + a);
+            const R qac = op_q<R>(op, a * N + c), qca = op_q<R>(op, c * N + a);
 #pragma unroll
             for (int k = 0; k < P::NV; ++k) {
                 t[a][k] = qac * F[k] + t[a][k];
@@ -116,6 +126,7 @@ template <int N>
 struct KernargOp {
     kernarg_ptr<OpArg<N>> a;
     __device__ double q(int i) const { return a->Q[i]; }
+    __device__ float qf(int i) const { return a->Qf[i]; }
     __device__ double w(int i) const { return a->w[i]; }
 };
 
@@ -126,6 +137,7 @@ template <int N>
 struct ParamOp {
     const OpArg<N> &a;
     __device__ double q(int i) const { return a.Q[i]; }
+    __device__ float qf(int i) const { return a.Qf[i]; }
     __device__ double w(int i) const { return a.w[i]; }
 };
 
@@ -139,6 +151,7 @@ struct TableOp {
         asm volatile("" : "+s"(p));
         return p[i];
     }
+    __device__ float qf(int i) const { return (float)q(i); }
     __device__ double w(int i) const { return W[i]; }
 };
 

@@ -114,9 +114,8 @@ int launch_surface(const VolumeRequest &r) {
     a.yf = r.yf;
     a.E = r.E;
     a.gamma = r.gamma;
-    for (int i = 0; i < N * N; ++i) a.op.Q[i] = r.op.Q[i];
+    fill_op_arg<N>(a.op, r.op);
     for (int i = 0; i < N; ++i) {
-        a.op.w[i] = r.op.w[i];
         a.ell[i] = r.op.lm[i];
         a.ell[N + i] = r.op.lp[i];
     }
@@ -189,8 +188,7 @@ int launch_curv(const VolumeRequest &r) {
     a.out = r.out;
     a.E = r.E;
     a.gamma = r.gamma;
-    for (int i = 0; i < N * N; ++i) a.op.Q[i] = r.op.Q[i];
-    for (int i = 0; i < N; ++i) a.op.w[i] = r.op.w[i];
+    fill_op_arg<N>(a.op, r.op);
     if (r.flux == SF_FLUX_EULER_CHANDRASHEKAR_PFIX)
         hipLaunchKernelGGL((sf_curv_kernel<N, EulerCurvPFixFP64>), dim3((unsigned)blocks), dim3(G::THREADS), 0,
                            r.stream, a);
