@@ -35,7 +35,10 @@ struct SurfaceWork {
         constexpr int T = DIM == 3 ? NN * NN : NN;  // facet nodes per face
         constexpr int NF = 2 * DIM;
         const size_t fstride = (size_t)E * NF * T;
-#pragma unroll
+        // fused at n = 8 the two faces run as a loop, one face's staging and
+        // sums live at a time (unrolled, that kernel spilled 12 bytes per lane)
+        constexpr int kFaceUnroll = (VOLUME && NN == 8) ? 1 : 2;
+#pragma unroll kFaceUnroll
         for (int s = 0; s < 2; ++s) {
             const size_t fidx = ((size_t)e * NF + 2 * M + s) * T + line;
             double uc[P::NV];
