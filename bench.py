@@ -281,7 +281,7 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per offered load")
     ap.add_argument("--legs", default="all",
-                    help="comma list of extra legs (fp32, dense, tensor, surface, curvilinear, entropy, uncollocated, graph, "
+                    help="comma list of extra legs (fp32, pfix, dense, tensor, surface, curvilinear, entropy, uncollocated, graph, "
                          "per_n, figure1, serving) or 'all'")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain device-to-device copy of the input's size (counter calibration)")
@@ -419,6 +419,22 @@ def main() -> int:
                                     "hbm_algorithmic_GBps": round(bytes32 / (k32 * 1e-3) / 1e9, 1),
                                     "hbm_frac": round(bytes32 / (k32 * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
             log(f"[bench] FP32-split: {ms32:.4f} ms/step ({ms_per_step / ms32:.2f}x FP64)")
+
+        if want("pfix"):
+            # the pressure-fix flux variant (FP64) on the same workload
+            outp = torch.empty_like(ut)
+
+            def stepp():
+                sfhad.volume(ut, n, 3, "euler_pfix", out=outp, stream=stream)
+
+            for _ in range(args.warmup):
+                stepp()
+            tp, kp = timed_launches(torch, stepp, args.steps, stream)
+            result["pfix"] = {"value": dof / (tp / args.steps * 1e-3), "unit": "DOF/s",
+                              "ms_per_step": tp / args.steps, "kernel_ms": kp,
+                              "vs_plain_flux": ms_per_step / (tp / args.steps)}
+            log(f"[bench] pressure-fix flux: {tp / args.steps:.4f} ms/step "
+                f"({ms_per_step / (tp / args.steps):.2f}x the plain flux's rate)")
 
         if want("dense"):
             # dense O(n^(2d)) GPU path on a 4096-element subset

@@ -113,12 +113,16 @@ struct Geom {
 //           1.22x FP32-split;
 //   n = 9:  one element per 4-wave block (243/256, grouped 81/128), FP64 held
 //           to 3 waves per SIMD: 2.0x;
+//   n = 10: two elements per 10-wave block (600/640 lanes, 124 KB of LDS: one
+//           block per CU, 10 waves, where the grouped 6-wave block of one
+//           element left 6): 1.19x FP64 (168 VGPRs, 52 bytes spilled),
+//           1.28x FP32-split, 1.18x pressure fix;
 //   n = 12, 13: one element per 7- and 8-wave block (432/448, 507/512): 1.5x
 //           and 1.6x (the grouped 9-wave blocks had to spill to fit).
 // n = 2, 3, 4, 8 fill their waves grouped.  Flat blocks of 5 or 6 waves
-// (n = 5 with 5 elements, n = 6 with 3, n = 7 with 2, n = 10) ran as if only
-// one block fitted per CU, and bounding registers below the natural count
-// (spilling) was slower, so n = 7, 10, 11 stay grouped.
+// (n = 5 with 5 elements, n = 6 with 3, n = 7 with 2, n = 10 with 1) ran as
+// if only one block fitted per CU, and bounding registers below the natural
+// count (spilling) was slower, so n = 7 and 11 stay grouped.
 struct VolumeShape {
     int fe;
     int min_waves;
@@ -128,6 +132,7 @@ constexpr VolumeShape euler_volume_shape(int n, bool fp64) {
     return n == 5 ? VolumeShape{fp64 ? 3 : 0, 1, false}
          : n == 6 ? VolumeShape{2, 1, true}
          : n == 9 ? VolumeShape{1, fp64 ? 3 : 1, false}
+         : n == 10 ? VolumeShape{2, 1, false}
          : (n == 12 || n == 13) ? VolumeShape{1, 1, false}
          : VolumeShape{0, 1, n <= 8};
 }
