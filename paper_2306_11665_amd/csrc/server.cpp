@@ -47,7 +47,6 @@ using Clock = std::chrono::steady_clock;
 
 constexpr size_t kAlign = 256;
 constexpr int kSlots = 2;  // 3 and 4 measured no better (p50/p99 within run-to-run spread)
-constexpr int kGridCap = 1024;  // persistent workgroups per variant node
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -252,7 +251,7 @@ public:
                 std::memcpy(a.inl, hdesc_[s] + first[v], sizeof(ServeDesc) * count[v]);
             }
             hipKernelNodeParams p = params_[s][v];
-            p.gridDim = dim3((unsigned)std::min<int64_t>(total[v], kGridCap));
+            p.gridDim = dim3((unsigned)total[v]);  // one workgroup per block of elements
             if (hipGraphExecKernelNodeSetParams(gexec_[s][v], node_[s][v], &p) != hipSuccess)
                 return fail_hip("graph node update");
             if (hipGraphLaunch(gexec_[s][v], st_[s]) != hipSuccess) return fail_hip("hipGraphLaunch");

@@ -213,12 +213,21 @@ def test_failed_batch_launch_reports_to_waiters(serving):
     with serving.Server(1 << 30, max_inflight=8, sim_us_per_block=50.0) as srv:
         m = srv.register(tiny_state(16, 4), 4)
         assert L.sf_server_sim_fail_launches(srv._h, 1) == 0
+        b0 = srv.batch_stats()[0]
         bad = [srv.submit(m.mesh_id) for _ in range(2)]
+        failed = []
         for t in bad:
-            with pytest.raises(sfhad.SFError) as e:
+            try:
                 srv.wait(t)
-            assert e.value.status == -3 and "launched" in str(e.value)
+                failed.append(False)
+            except sfhad.SFError as e:
+                assert e.status == -3 and "launched" in str(e)
+                failed.append(True)
             srv.release(t)
+        # the first request is in the failed batch; the second joined it, or
+        # (when the scheduler woke between the two submissions) ran in the next one
+        assert failed[0]
+        assert failed[1] == (srv.batch_stats()[0] - b0 == 1)
         good = srv.submit(m.mesh_id)
         srv.wait(good)
         srv.release(good)
