@@ -206,10 +206,17 @@ int dispatch_tensor(const TensorRequest &r) {
 // floor(x / d) = mulhi(x, ceil(2^32 / d)) exactly when x e < 2^32,
 // e = ceil(2^32 / d) d - 2^32 < d (write x = q d + r: the product is
 // q + r/d + x e / (d 2^32), below q + 1 when r <= d - 1 and x e < 2^32).
-// Here d <= 4352 and x <= 4352 (an index inside the block's LDS stage or
-// its lines), so x e < 2^25.
+// Here d <= 4352 and x <= 4352 (an index inside the block's LDS stage of
+// at most kRectStage values plus pads, or its lines), so x e < 2^25.
 constexpr int kRectTPW = 8;       // 16-line tiles per wave and pass (at most)
-constexpr int kRectStage = 4096;  // LDS doubles per block for the slabs (plus pads)
+constexpr int kRectStage = 4096;  // LDS doubles per block for the slabs (plus pads), run-time sizes
+// The same for the compile-time size pairs, from A/B runs on MI355X against
+// 4096: 6144 (more slabs per block) ran 1.03-1.17x faster for every pair
+// measured (3 -> 5 up to 9 -> 7) but the projection from 10^3 nodes, which
+// ran faster with fewer (3072: 1.07x at 10 -> 8; 6144: 0.93x).
+__host__ __device__ constexpr int rect_stage(int ni, int no) {
+    return (ni > no && ni * ni * ni >= 1000) ? 3072 : 6144;
+}
 
 struct RectArgs {
     const double *in;
@@ -229,12 +236,12 @@ __host__ __device__ constexpr uint32_t rect_rc(int64_t d) {
     return (uint32_t)(((int64_t)1 << 32) / d + ((((int64_t)1 << 32) % d) != 0));
 }
 __host__ __device__ constexpr int rect_pow(int b, int e) { return e == 0 ? 1 : b * rect_pow(b, e - 1); }
-// slabs per block: the LDS stage holds kRectStage doubles, and the lines of
-// a pass fill at most 4 waves x kRectTPW tiles of 16
-__host__ __device__ constexpr int rect_slabs_per_block(int ni, int no, int d) {
+// slabs per block: the LDS stage holds `stage` doubles, and the lines of a
+// pass fill at most 4 waves x kRectTPW tiles of 16
+__host__ __device__ constexpr int rect_slabs_per_block(int ni, int no, int d, int stage) {
     const int mx = ni > no ? ni : no;
     const int mxd = rect_pow(mx, d), mxl = rect_pow(mx, d - 1);
-    const int g1 = kRectStage / mxd, g2 = 64 * kRectTPW / mxl;
+    const int g1 = stage / mxd, g2 = 64 * kRectTPW / mxl;
     const int g = g1 < g2 ? g1 : g2;
     return g < 1 ? 1 : g;
 }
@@ -249,7 +256,8 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
     constexpr bool CT = NI > 0 && NO > 0;
     constexpr int MX = NI > NO ? NI : NO;
     const int ni = CT ? NI : A->ni, no = CT ? NO : A->no;
-    const int G = CT ? rect_slabs_per_block(NI, NO, DIM) : A->G;
+    constexpr int STAGE = CT ? rect_stage(NI, NO) : kRectStage;
+    const int G = CT ? rect_slabs_per_block(NI, NO, DIM, STAGE) : A->G;
     const int cap = CT ? rect_pow(MX, DIM) + rect_pow(MX, DIM - 1) : A->cap;
     const uint32_t rc_ni = CT ? rect_rc(NI) : A->rc_ni, rc_no = CT ? rect_rc(NO) : A->rc_no;
     const uint32_t rc_nin = CT ? rect_rc(rect_pow(NI, DIM)) : A->rc_nin;
@@ -265,7 +273,7 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
     const double *src = A->in + s0 * nin;
     // stage 0: the input slabs, x fastest, one pad per x-row of n_in; every
     // load is issued before the first LDS store
-    constexpr int SPT = kRectStage / kTensorThreads;
+    constexpr int SPT = STAGE / kTensorThreads;
     const int total = gs * nin;
     double v[SPT];
 #pragma unroll
@@ -399,7 +407,6 @@ int launch_tensor_rect(const TensorRequest &r) {
     a.slabs = r.E * r.nvar;
     a.ni = r.n;
     a.no = r.n_out;
-    a.G = rect_slabs_per_block(r.n, r.n_out, r.d);
     const int mx = r.n > r.n_out ? r.n : r.n_out;
     a.cap = rect_pow(mx, r.d) + rect_pow(mx, r.d - 1);
     a.rc_ni = rect_rc(r.n);
@@ -412,12 +419,6 @@ int launch_tensor_rect(const TensorRequest &r) {
         a.rc_lps[m] = m < r.d ? rect_rc(lps) : 0;
     }
     for (int i = 0; i < r.n_out * r.n; ++i) a.M[i] = r.M[i];
-    const int64_t blocks = (a.slabs + a.G - 1) / a.G;
-    if (blocks > 0x7fffffffLL) {
-        set_error("too many elements for one launch");
-        return SF_ERR_UNSUPPORTED;
-    }
-    const size_t lds = sizeof(double) * (size_t)a.G * a.cap;
     // compile-time sizes for the over-integration pairs of the modal path
     // (n modes <-> n + 2 quadrature nodes, n = 3..8, 3D); run-time otherwise
     const void *fn = nullptr;
@@ -427,10 +428,15 @@ int launch_tensor_rect(const TensorRequest &r) {
         SF_RECT(3, 5) SF_RECT(5, 3) SF_RECT(4, 6) SF_RECT(6, 4) SF_RECT(5, 7) SF_RECT(7, 5)
         SF_RECT(6, 8) SF_RECT(8, 6) SF_RECT(7, 9) SF_RECT(9, 7) SF_RECT(8, 10) SF_RECT(10, 8)
 #undef SF_RECT
-        if (!fn) fn = reinterpret_cast<const void *>(&tensor_rect_kernel<3, 0, 0>);
-    } else {
-        fn = reinterpret_cast<const void *>(&tensor_rect_kernel<2, 0, 0>);
     }
+    a.G = rect_slabs_per_block(r.n, r.n_out, r.d, fn ? rect_stage(r.n, r.n_out) : kRectStage);
+    if (!fn) fn = reinterpret_cast<const void *>(r.d == 3 ? &tensor_rect_kernel<3, 0, 0> : &tensor_rect_kernel<2, 0, 0>);
+    const int64_t blocks = (a.slabs + a.G - 1) / a.G;
+    if (blocks > 0x7fffffffLL) {
+        set_error("too many elements for one launch");
+        return SF_ERR_UNSUPPORTED;
+    }
+    const size_t lds = sizeof(double) * (size_t)a.G * a.cap;
     void *kp[] = {&a};
     if (hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(kTensorThreads), kp, lds, r.stream) != hipSuccess) {
         set_error(std::string("tensor_rect_kernel launch: ") + hipGetErrorString(hipGetLastError()));
