@@ -53,7 +53,7 @@ def test_alone_equals_mix(env):
                 srv.release(t)
         rng = np.random.default_rng(1301)
         count = 96
-        arr, which = W.poisson_arrivals(20000.0, count, len(meshes), seed=1302)
+        arr, which = W.poisson_arrivals(40000.0, count, len(meshes), seed=1302)   # ~25 us apart: well inside one request's latency
         precs = rng.choice(["fp64", "fp32_split"], size=count)
         # run both precisions in one mix: submit per request with its precision
         tickets = []
