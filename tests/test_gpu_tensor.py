@@ -134,16 +134,34 @@ def test_full_size_sampled_and_round_trip(torch_dev, sf, orc):
     assert relerr(uh_np[:, idx, :], ref) <= TOL
 
 
-@pytest.mark.parametrize("ni,no,d", [(3, 5, 2), (4, 6, 3), (5, 3, 3), (2, 16, 2), (8, 12, 3), (16, 9, 3),
-                                     (7, 8, 3), (4, 16, 3)])
+# the (n_in, n_out) pairs built with compile-time sizes (3D), each with its
+# own LDS stage of `rect_stage` doubles; other pairs take 4096
+CT_PAIRS = [(3, 5), (5, 3), (4, 6), (6, 4), (5, 7), (7, 5), (6, 8), (8, 6), (7, 9), (9, 7), (8, 10), (10, 8)]
+
+
+def rect_block_slabs(ni, no, d):
+    """Slabs per block of the rectangular kernel's launch: the LDS stage
+    (3072 doubles for 10 -> 8 and larger projections, 6144 for the other
+    compile-time pairs, 4096 otherwise) over the larger shape, at most 512
+    lines of a pass."""
+    mx = max(ni, no)
+    if d == 3 and (ni, no) in CT_PAIRS:
+        stage = 3072 if (ni > no and ni ** 3 >= 1000) else 6144
+    else:
+        stage = 4096
+    return max(1, min(stage // mx ** d, 512 // mx ** (d - 1)))
+
+
+@pytest.mark.parametrize("ni,no,d", [(3, 5, 2), (2, 16, 2), (8, 12, 3), (16, 9, 3), (7, 8, 3), (4, 16, 3)]
+                         + [(a, b, 3) for a, b in CT_PAIRS])
 def test_rectangular_every_shape_class(torch_dev, sf, orc, ni, no, d):
     """n_in != n_out (modes to more or fewer nodes): several blocks and a
-    ragged last one, a non-symmetric matrix, against the oracle."""
+    ragged last one, a non-symmetric matrix, against the oracle; every
+    compile-time pair and the run-time kernel in 2D and 3D."""
     rng = np.random.default_rng(ni * 31 + no + d)
     M = rng.normal(size=(no, ni))
     nvar = 5
-    mx = max(ni, no)
-    G = max(1, min(4096 // mx ** d, 512 // mx ** (d - 1)))
+    G = rect_block_slabs(ni, no, d)
     slabs = 3 * G + 1
     E = -(-slabs // nvar)
     u = rng.normal(size=(nvar, E, ni ** d))
