@@ -51,25 +51,23 @@ serve_kernel(const ServeArgs) {
     // of spills per lane and 0.86 of this form's burst throughput)
     const int b = blockIdx.x;
     if (b >= A->total) return;
-    {
-        int lo = 0, hi = ndesc - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (dd[mid].blk_begin <= b) lo = mid; else hi = mid - 1;
-        }
-        lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: keep the descriptor scalar
-        GDesc &D = dd[lo];
-        const int off = __builtin_amdgcn_readfirstlane(serve_table_off(D.node_kind, N));
-        const TableOp op{A->optab + off, A->optab + off + N * N};
-        // gamma is uniform per descriptor: keep it (and the flux constants
-        // derived from it) in scalar registers
-        const int64_t gbits = __builtin_bit_cast(int64_t, D.gamma);
-        const int glo = __builtin_amdgcn_readfirstlane((int)(gbits & 0xffffffff));
-        const int ghi = __builtin_amdgcn_readfirstlane((int)(gbits >> 32));
-        const double gamma = __builtin_bit_cast(double, ((int64_t)ghi << 32) | (uint32_t)glo);
-        sf_block<N, 3, P, FE>(D.u, D.out, D.E, (b - D.blk_begin) * Geom<N, 3, FE>::EPB, op, gamma, lds, sref,
-                              VolumeWorkT<serve_ahead<N, P>()>{});
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (dd[mid].blk_begin <= b) lo = mid; else hi = mid - 1;
     }
+    lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: keep the descriptor scalar
+    GDesc &D = dd[lo];
+    const int off = __builtin_amdgcn_readfirstlane(serve_table_off(D.node_kind, N));
+    const TableOp op{A->optab + off, A->optab + off + N * N};
+    // gamma is uniform per descriptor: keep it (and the flux constants
+    // derived from it) in scalar registers
+    const int64_t gbits = __builtin_bit_cast(int64_t, D.gamma);
+    const int glo = __builtin_amdgcn_readfirstlane((int)(gbits & 0xffffffff));
+    const int ghi = __builtin_amdgcn_readfirstlane((int)(gbits >> 32));
+    const double gamma = __builtin_bit_cast(double, ((int64_t)ghi << 32) | (uint32_t)glo);
+    sf_block<N, 3, P, FE>(D.u, D.out, D.E, (b - D.blk_begin) * Geom<N, 3, FE>::EPB, op, gamma, lds, sref,
+                          VolumeWorkT<serve_ahead<N, P>()>{});
 }
 
 }  // namespace dev

@@ -10,8 +10,9 @@
 //    whole budget is rejected at submission (SF_ERR_BUDGET).
 //  * Every scheduler tick packs all admitted, not yet launched requests into
 //    one batch on a free launch slot (two slots on two streams, so a new
-//    batch starts while the previous one drains): one persistent kernel per
-//    (precision, n) variant present, each a pre-built one-node hipGraph
+//    batch starts while the previous one drains): one serving kernel launch
+//    per (precision, n) variant present (one workgroup per block of
+//    elements of its requests), each a pre-built one-node hipGraph
 //    replayed with the batch's grid and arguments -- its requests'
 //    descriptors in the kernel arguments (or, for large batches, copied once
 //    to the device).  Requests that arrive while a batch runs go into the
@@ -198,7 +199,7 @@ public:
 
     // One launch per (precision, n) variant of the batch, in order of
     // decreasing work, on the slot's stream, then the slot's event.  Each
-    // (slot, variant) owns a one-node graph of its persistent kernel; a
+    // (slot, variant) owns a one-node graph of its serving kernel; a
     // launch sets the node's grid and arguments and replays it.  A variant's
     // descriptors (grouped, blk_begin counted per variant) go in the kernel
     // arguments when there are at most kServeInline of them; otherwise the

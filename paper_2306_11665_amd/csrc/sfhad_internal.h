@@ -63,7 +63,7 @@ int launch_dense_volume(const VolumeRequest &r);
 
 // ---------------------------------------------------------------------------
 // Serving kernel interface (volume_kernels.hip).
-// One request of a batch as the persistent kernel sees it.
+// One request of a batch as the serving kernel sees it.
 struct ServeDesc {
     const double *u;     // device state, 5 x E x n^3 (Euler, SoA)
     double *out;         // device output, same layout
@@ -83,7 +83,7 @@ int64_t serve_blocks(int n, int prec, int64_t E);
 // Size in doubles of the operator table and its host-side filling.
 int serve_optable_doubles();
 void serve_fill_optable(double *host);
-// The persistent serving kernel of variant v = prec * 7 + (n - 2); its only
+// The serving kernel of variant v = prec * 7 + (n - 2); its only
 // argument is a ServeArgs, passed by value.
 constexpr int kServeVariants = 14;
 inline int serve_variant(int n, int prec) { return prec * (kServeMaxN - 1) + (n - 2); }
