@@ -38,12 +38,24 @@ struct SurfaceWork {
         // fused at n = 8 the two faces run as a loop, one face's staging and
         // sums live at a time (unrolled, that kernel spilled 12 bytes per lane)
         constexpr int kFaceUnroll = (VOLUME && NN == 8) ? 1 : 2;
+        // surface alone: both faces' facet states are loaded before the
+        // first face's work (one memory latency per line instead of two)
+        constexpr bool kBothFirst = !VOLUME;
+        double ucb[2][P::NV];
+        if constexpr (kBothFirst) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const size_t fidx = ((size_t)e * NF + 2 * M + s) * T + line;
+#pragma unroll
+                for (int v = 0; v < P::NV; ++v) ucb[s][v] = uf[v * fstride + fidx];
+            }
+        }
 #pragma unroll kFaceUnroll
         for (int s = 0; s < 2; ++s) {
             const size_t fidx = ((size_t)e * NF + 2 * M + s) * T + line;
             double uc[P::NV];
 #pragma unroll
-            for (int v = 0; v < P::NV; ++v) uc[v] = uf[v * fstride + fidx];
+            for (int v = 0; v < P::NV; ++v) uc[v] = kBothFirst ? ucb[s][v] : uf[v * fstride + fidx];
             R sa[P::NS];
             P::stage(uc, ref, gamma, sa);
             const typename P::Node A = P::load(sa, 1, 0, M);
