@@ -261,6 +261,33 @@ int sf_tensor_apply(const double *in, int64_t elem_count, int n, int d, int nvar
 int sf_tensor_apply_rect(const double *in, int64_t elem_count, int n_in, int n_out, int d, int nvar,
                          const double *M_host, double *out, void *stream);
 
+/* Pointwise maps of 3D Euler states (as sf_entropy_variables and
+ * sf_conserved_variables below). */
+typedef enum {
+    SF_MAP_NONE = 0,
+    SF_MAP_ENTROPY_VARIABLES = 1,   /* conserved u -> entropy variables v(u) */
+    SF_MAP_CONSERVED_VARIABLES = 2  /* entropy variables v -> conserved u(v) */
+} sf_post_map;
+
+/* sf_tensor_apply_rect followed by a pointwise map of every output node, in
+ * one pass: out = map((M (x) M (x) M) in) for the 5 variables of each of the
+ * elem_count elements (d = 3, nvar = 5 implied; layouts as above).  The
+ * interpolation steps of the uncollocated modal path, to the n + 2 quadrature
+ * nodes of the over-integration (the proof of Theorem 1): u_q = V u_hat with
+ * v(u_q), and u(V P v) with the map back.  The map is the same code as the
+ * separate map calls, so the result is the same as sf_tensor_apply_rect then
+ * sf_entropy_variables (or sf_conserved_variables), bit for bit, without
+ * writing and re-reading the intermediate array.
+ *   map       SF_MAP_ENTROPY_VARIABLES or SF_MAP_CONSERVED_VARIABLES
+ *   n_out     n_in + 2 with 3 <= n_in <= 8 (else SF_ERR_UNSUPPORTED)
+ *   gamma     > 1 (the ratio of specific heats of the map)
+ *   out       must not overlap in.
+ * States must be physical (rho > 0, p > 0 after the interpolation; -v_4 > 0
+ * for the map back); otherwise NaN or Inf propagate as in the map calls.
+ * Errors as for sf_tensor_apply_rect. */
+int sf_tensor_apply_rect_map(const double *in, int64_t elem_count, int n_in, int n_out, int map, double gamma,
+                             const double *M_host, double *out, void *stream);
+
 /* n_modes orthonormal Legendre modes on the m_nodes nodes of node_kind:
  * V_host (m_nodes x n_modes) and the L2 projection P_host
  * = (V^T W V)^{-1} V^T W (n_modes x m_nodes), with P V = I; for

@@ -333,6 +333,38 @@ int sf_tensor_apply_rect(const double *in, int64_t E, int n_in, int n_out, int d
     return launch_tensor_apply(r);
 }
 
+int sf_tensor_apply_rect_map(const double *in, int64_t E, int n_in, int n_out, int map, double gamma,
+                             const double *M_host, double *out, void *stream) {
+    if (map != SF_MAP_ENTROPY_VARIABLES && map != SF_MAP_CONSERVED_VARIABLES)
+        return fail(SF_ERR_ARG, "map must be SF_MAP_ENTROPY_VARIABLES or SF_MAP_CONSERVED_VARIABLES");
+    if (!(gamma > 1.0) || !std::isfinite(gamma)) return fail(SF_ERR_ARG, "gamma must be finite and > 1");
+    if (E < 0) return fail(SF_ERR_ARG, "elem_count must be >= 0");
+    if (!M_host) return fail(SF_ERR_ARG, "null M_host");
+    if (n_in < 3 || n_in > 8 || n_out != n_in + 2)
+        return fail(SF_ERR_UNSUPPORTED, "the fused map is built for n_in in [3, 8] and n_out = n_in + 2");
+    for (int i = 0; i < n_in * n_out; ++i)
+        if (!std::isfinite(M_host[i])) return fail(SF_ERR_ARG, "M_host has a non-finite entry");
+    const int64_t NI = ipow(n_in, 3), NO = ipow(n_out, 3);
+    if (E > 0 && E > INT64_MAX / (NO * 5 * (int64_t)sizeof(double))) return fail(SF_ERR_ARG, "elem_count too large");
+    if (E == 0) return SF_OK;
+    if (!in || !out) return fail(SF_ERR_ARG, "null in or out");
+    if (overlaps(in, (size_t)(NI * 5 * E) * sizeof(double), out, (size_t)(NO * 5 * E) * sizeof(double)))
+        return fail(SF_ERR_ARG, "out overlaps in");
+    TensorRequest r;
+    r.in = in;
+    r.out = out;
+    r.E = E;
+    r.n = n_in;
+    r.n_out = n_out;
+    r.d = 3;
+    r.nvar = 5;
+    r.post_map = map;
+    r.gamma = gamma;
+    r.stream = reinterpret_cast<hipStream_t>(stream);
+    for (int i = 0; i < n_in * n_out; ++i) r.M[i] = M_host[i];
+    return launch_tensor_apply(r);
+}
+
 int sf_tensor_apply(const double *in, int64_t E, int n, int d, int nvar, const double *M_host, double *out,
                     void *stream) {
     return sf_tensor_apply_rect(in, E, n, n, d, nvar, M_host, out, stream);

@@ -17,6 +17,7 @@
 // and exponentials (ocml, full FP64 accuracy) make it about as much VALU- as
 // HBM-bound.  Quotients are products with a refined reciprocal (about one
 // ulp), the 1/(gamma - 1) factors one reciprocal per thread.
+#include "entropy_maps.h"
 #include "kernels_common.h"
 #include "sfhad_internal.h"
 
@@ -146,40 +147,14 @@ __global__ void __launch_bounds__(256) entropy_map_kernel(const double *__restri
     const double igm1 = 1.0 / (g - 1.0);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const double x0 = in[i], x1 = in[count + i], x2 = in[2 * count + i], x3 = in[3 * count + i],
-                     x4 = in[4 * count + i];
-        double y0, y1, y2, y3, y4;
-        if (dir == 0) {
-            const double irho = rcp_fine(x0);
-            const double vx = x1 * irho, vy = x2 * irho, vz = x3 * irho;
-            const double q = vx * vx + vy * vy + vz * vz;
-            const double p = (g - 1.0) * (x4 - 0.5 * x0 * q);
-            const double rp = x0 * rcp_fine(p);
-            const double s = log(p) - g * log(x0);
-            y0 = (g - s) * igm1 - 0.5 * rp * q;
-            y1 = rp * vx;
-            y2 = rp * vy;
-            y3 = rp * vz;
-            y4 = -rp;
-        } else {
-            const double rp = -x4;
-            const double irp = rcp_fine(rp);
-            const double vx = x1 * irp, vy = x2 * irp, vz = x3 * irp;
-            const double q = vx * vx + vy * vy + vz * vz;
-            const double s = g - (g - 1.0) * (x0 + 0.5 * rp * q);
-            const double rho = exp(-(s + log(rp)) * igm1);
-            const double p = rho * irp;
-            y0 = rho;
-            y1 = rho * vx;
-            y2 = rho * vy;
-            y3 = rho * vz;
-            y4 = p * igm1 + 0.5 * rho * q;
-        }
-        out[i] = y0;
-        out[count + i] = y1;
-        out[2 * count + i] = y2;
-        out[3 * count + i] = y3;
-        out[4 * count + i] = y4;
+        const double x[5] = {in[i], in[count + i], in[2 * count + i], in[3 * count + i], in[4 * count + i]};
+        double y[5];
+        if (dir == 0)
+            entropy_from_conserved(x, g, igm1, y);
+        else
+            conserved_from_entropy(x, g, igm1, y);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) out[c * count + i] = y[c];
     }
 }
 

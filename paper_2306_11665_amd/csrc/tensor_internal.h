@@ -18,6 +18,8 @@ struct TensorRequest {
     int d = 0;
     int nvar = 0;
     hipStream_t stream = nullptr;
+    int post_map = 0;  // 0, or a pointwise map applied to every output node (sf_post_map)
+    double gamma = 1.4;
     double M[kMaxN * kMaxN];
 };
 

@@ -22,6 +22,7 @@
 // the loads in flight, per CU.  A block only writes the slabs it read, after
 // a barrier, so in == out is allowed.
 #include "kernels_common.h"
+#include "entropy_maps.h"
 #include "tensor_internal.h"
 
 namespace sfhad {
@@ -222,6 +223,7 @@ struct RectArgs {
     const double *in;
     double *out;
     int64_t slabs;
+    double gamma;  // the fused pointwise map's (MAP != 0)
     int ni, no, G, cap;  // sizes, slabs per block, LDS doubles per slab
     uint32_t rc_ni, rc_no, rc_nin;  // ceil(2^32 / d) of n_in, n_out, n_in^d
     uint32_t rc_lps[3];             // of the lines per slab of pass m
@@ -246,18 +248,29 @@ __host__ __device__ constexpr int rect_slabs_per_block(int ni, int no, int d, in
     return g < 1 ? 1 : g;
 }
 
+// Slabs per block of the fused form: the 5 variables of whole elements.
+__host__ __device__ constexpr int rect_map_slabs_per_block(int ni, int no) {
+    return rect_slabs_per_block(ni, no, 3, rect_stage(ni, no)) / 5 * 5;
+}
+
 // NI, NO > 0: the sizes as compile-time constants (every index split and
 // product folds into shifts and constant multiplies); 0: run-time sizes
-// from the arguments.  The code is the same.
-template <int DIM, int NI, int NO>
+// from the arguments.  The code is the same.  MAP != 0 (3D Euler, 5
+// variables, interpolation to more nodes): a block takes the 5 variable
+// slabs of whole elements, keeps the last pass in LDS and applies a
+// pointwise map to each output node before the store -- conserved to
+// entropy variables (MAP = 1) or back (MAP = 2) -- so the map costs no
+// separate pass over HBM.
+template <int DIM, int NI, int NO, int MAP = 0>
 __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectArgs) {
     extern __shared__ double buf[];
     const auto A = kernel_args<RectArgs>();
     constexpr bool CT = NI > 0 && NO > 0;
+    static_assert(MAP == 0 || (CT && DIM == 3 && NI < NO), "the fused map is built for 3D interpolation");
     constexpr int MX = NI > NO ? NI : NO;
     const int ni = CT ? NI : A->ni, no = CT ? NO : A->no;
     constexpr int STAGE = CT ? rect_stage(NI, NO) : kRectStage;
-    const int G = CT ? rect_slabs_per_block(NI, NO, DIM, STAGE) : A->G;
+    const int G = MAP ? rect_map_slabs_per_block(NI, NO) : (CT ? rect_slabs_per_block(NI, NO, DIM, STAGE) : A->G);
     const int cap = CT ? rect_pow(MX, DIM) + rect_pow(MX, DIM - 1) : A->cap;
     const uint32_t rc_ni = CT ? rect_rc(NI) : A->rc_ni, rc_no = CT ? rect_rc(NO) : A->rc_no;
     const uint32_t rc_nin = CT ? rect_rc(rect_pow(NI, DIM)) : A->rc_nin;
@@ -268,8 +281,14 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
         nin *= ni;
         nout *= no;
     }
+    // slabs of this block: s0 .. s0 + gs - 1; with MAP, element-major over the
+    // block's elements e0 .. e0 + gs/5 - 1 (block slab g = 5 el + var is the
+    // global slab var * E + e0 + el)
+    const int64_t E5 = A->slabs / 5;
     const int64_t s0 = (int64_t)blockIdx.x * G;
-    const int gs = (int)((A->slabs - s0) < G ? (A->slabs - s0) : G);
+    const int64_t e0 = (int64_t)blockIdx.x * (G / 5);
+    const int gs = MAP ? 5 * (int)((E5 - e0) < G / 5 ? (E5 - e0) : G / 5)
+                       : (int)((A->slabs - s0) < G ? (A->slabs - s0) : G);
     const double *src = A->in + s0 * nin;
     // stage 0: the input slabs, x fastest, one pad per x-row of n_in; every
     // load is issued before the first LDS store
@@ -279,7 +298,14 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
         const int i = tid + j * kTensorThreads;
-        if (i < total) v[j] = src[i];
+        if (i < total) {
+            if constexpr (MAP != 0) {
+                const int g = qdiv(i, rc_nin), lin = i - m24(g, nin);
+                v[j] = A->in[((int64_t)(g % 5) * E5 + e0 + g / 5) * nin + lin];
+            } else {
+                v[j] = src[i];
+            }
+        }
     }
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
@@ -324,6 +350,7 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
         const int str_in = m == 0 ? 1 : (m == 1 ? si1 : si2);
         const int str_out = m == 0 ? 1 : (m == 1 ? so1 : so2);
         const int str_g = m == 0 ? 1 : (m == 1 ? sg1 : sg2);
+        const bool to_lds = m < DIM - 1 || MAP != 0;  // this pass's results stay in LDS
         d4 acc[kRectTPW];
         int bout[kRectTPW];  // output base: LDS index, or the element offset in `out`
         bool ok[kRectTPW];
@@ -356,8 +383,8 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
                 L = qk;
             }
             const int bin = m24(g, cap) + c[0] + m24(si1, c[1]) + m24(si2, c[2]);
-            bout[u] = m == DIM - 1 ? m24(g, nout) + c[0] + m24(sg1, c[1]) + m24(sg2, c[2])
-                                   : m24(g, cap) + c[0] + m24(so1, c[1]) + m24(so2, c[2]);
+            bout[u] = !to_lds ? m24(g, nout) + c[0] + m24(sg1, c[1]) + m24(sg2, c[2])
+                              : m24(g, cap) + c[0] + m24(so1, c[1]) + m24(so2, c[2]);
             // the tile's B operands first (up to 4 LDS reads in flight), then
             // the MFMAs; ks is wave-uniform
             double b[4];
@@ -370,7 +397,7 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
             for (int s = 0; s < 4; ++s)
                 if (s < ks) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc[u], 0, 0, 0);
         }
-        if (m < DIM - 1) __syncthreads();  // every read of this pass is done
+        if (to_lds) __syncthreads();  // every read of this pass is done
         double *dst = A->out + s0 * nout;
 #pragma unroll
         for (int u = 0; u < kRectTPW; ++u) {
@@ -379,20 +406,40 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
             for (int r = 0; r < 4; ++r) {
                 const int q = 4 * r + kq;
                 if (q >= no) continue;
-                if (m == DIM - 1)
+                if (!to_lds)
                     dst[bout[u] + m24(q, str_g)] = acc[u][r];
                 else
                     buf[bout[u] + m24(q, str_out)] = acc[u][r];
             }
         }
-        if (m < DIM - 1) __syncthreads();
+        if (to_lds) __syncthreads();
+    }
+    if constexpr (MAP != 0) {
+        // the block's output nodes, node fastest (coalesced stores); the last
+        // pass left node (x, y, z) of slab g at g cap + node + node / n_out
+        const double gam = A->gamma;
+        const double igm1 = 1.0 / (gam - 1.0);
+        const int nel = gs / 5;
+        for (int j = tid; j < nel * nout; j += kTensorThreads) {
+            const int el = j / nout, node = j - el * nout;
+            const int li = node + node / no;
+            double x[5], y[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) x[c] = buf[m24(5 * el + c, cap) + li];
+            if (MAP == 1)
+                entropy_from_conserved(x, gam, igm1, y);
+            else
+                conserved_from_entropy(x, gam, igm1, y);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) A->out[((int64_t)c * E5 + e0 + el) * nout + node] = y[c];
+        }
     }
 }
 
 }  // namespace dev
 
 int launch_tensor_apply(const TensorRequest &r) {
-    if (r.n_out != r.n) return launch_tensor_rect(r);
+    if (r.n_out != r.n || r.post_map != SF_MAP_NONE) return launch_tensor_rect(r);
     if (r.d == 2) return dev::dispatch_tensor<2>(r);
     if (r.d == 3) return dev::dispatch_tensor<3>(r);
     set_error("d must be 2 or 3");
@@ -419,19 +466,37 @@ int launch_tensor_rect(const TensorRequest &r) {
         a.rc_lps[m] = m < r.d ? rect_rc(lps) : 0;
     }
     for (int i = 0; i < r.n_out * r.n; ++i) a.M[i] = r.M[i];
+    a.gamma = r.gamma;
     // compile-time sizes for the over-integration pairs of the modal path
     // (n modes <-> n + 2 quadrature nodes, n = 3..8, 3D); run-time otherwise
     const void *fn = nullptr;
-    if (r.d == 3) {
+    if (r.post_map != SF_MAP_NONE) {
+        // the fused map: interpolation n -> n + 2 (3D, 5 variables) only
+        if (r.d != 3 || r.nvar != 5 || r.n_out != r.n + 2 || r.n < 3 || r.n > 8) {
+            set_error("the fused map is built for 3D Euler states and n -> n + 2 nodes, n = 3..8");
+            return SF_ERR_UNSUPPORTED;
+        }
+#define SF_RECT_MAP(NI_, NO_)                                                                              \
+        if (r.n == NI_)                                                                                    \
+            fn = r.post_map == SF_MAP_ENTROPY_VARIABLES                                                    \
+                     ? reinterpret_cast<const void *>(&tensor_rect_kernel<3, NI_, NO_, SF_MAP_ENTROPY_VARIABLES>) \
+                     : reinterpret_cast<const void *>(&tensor_rect_kernel<3, NI_, NO_, SF_MAP_CONSERVED_VARIABLES>);
+        SF_RECT_MAP(3, 5) SF_RECT_MAP(4, 6) SF_RECT_MAP(5, 7) SF_RECT_MAP(6, 8) SF_RECT_MAP(7, 9) SF_RECT_MAP(8, 10)
+#undef SF_RECT_MAP
+        a.G = rect_map_slabs_per_block(r.n, r.n_out);
+    } else {
+        if (r.d == 3) {
 #define SF_RECT(NI_, NO_) \
-        if (r.n == NI_ && r.n_out == NO_) fn = reinterpret_cast<const void *>(&tensor_rect_kernel<3, NI_, NO_>);
-        SF_RECT(3, 5) SF_RECT(5, 3) SF_RECT(4, 6) SF_RECT(6, 4) SF_RECT(5, 7) SF_RECT(7, 5)
-        SF_RECT(6, 8) SF_RECT(8, 6) SF_RECT(7, 9) SF_RECT(9, 7) SF_RECT(8, 10) SF_RECT(10, 8)
+            if (r.n == NI_ && r.n_out == NO_) fn = reinterpret_cast<const void *>(&tensor_rect_kernel<3, NI_, NO_>);
+            SF_RECT(3, 5) SF_RECT(5, 3) SF_RECT(4, 6) SF_RECT(6, 4) SF_RECT(5, 7) SF_RECT(7, 5)
+            SF_RECT(6, 8) SF_RECT(8, 6) SF_RECT(7, 9) SF_RECT(9, 7) SF_RECT(8, 10) SF_RECT(10, 8)
 #undef SF_RECT
+        }
+        a.G = rect_slabs_per_block(r.n, r.n_out, r.d, fn ? rect_stage(r.n, r.n_out) : kRectStage);
+        if (!fn)
+            fn = reinterpret_cast<const void *>(r.d == 3 ? &tensor_rect_kernel<3, 0, 0> : &tensor_rect_kernel<2, 0, 0>);
     }
-    a.G = rect_slabs_per_block(r.n, r.n_out, r.d, fn ? rect_stage(r.n, r.n_out) : kRectStage);
-    if (!fn) fn = reinterpret_cast<const void *>(r.d == 3 ? &tensor_rect_kernel<3, 0, 0> : &tensor_rect_kernel<2, 0, 0>);
-    const int64_t blocks = (a.slabs + a.G - 1) / a.G;
+    const int64_t blocks = r.post_map != SF_MAP_NONE ? (r.E + a.G / 5 - 1) / (a.G / 5) : (a.slabs + a.G - 1) / a.G;
     if (blocks > 0x7fffffffLL) {
         set_error("too many elements for one launch");
         return SF_ERR_UNSUPPORTED;

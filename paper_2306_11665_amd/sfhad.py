@@ -100,6 +100,8 @@ def lib() -> ctypes.CDLL:
         L.sf_tensor_apply.restype = ci
         L.sf_tensor_apply_rect.argtypes = [vp, i64, ci, ci, ci, ci, _dp, vp, vp]
         L.sf_tensor_apply_rect.restype = ci
+        L.sf_tensor_apply_rect_map.argtypes = [vp, i64, ci, ci, ci, ctypes.c_double, _dp, vp, vp]
+        L.sf_tensor_apply_rect_map.restype = ci
         L.sf_basis_rect.argtypes = [ci, ci, ci, _dp, _dp]
         L.sf_basis_rect.restype = ci
         L.sf_diag_log1p.argtypes = [vp, i64, vp, vp]
@@ -355,6 +357,37 @@ def tensor_apply(u, n: int, d: int, M, *, out=None, stream=None):
         raise ValueError(f"out must be a contiguous float64 tensor {shape} on u's device")
     check(lib().sf_tensor_apply_rect(u.data_ptr(), u.shape[1], n, n_out, d, u.shape[0], Mh.ctypes.data_as(_dp),
                                      out.data_ptr(), _stream_handle(stream)), "sf_tensor_apply_rect")
+    _record(stream, u, out)
+    return out
+
+
+POST_MAP = {"entropy": 1, "conserved": 2}
+
+
+def tensor_apply_map(u, n: int, M, post_map: str, *, gamma=1.4, out=None, stream=None):
+    """out = map((M kron M kron M) u) in one pass (sf_tensor_apply_rect_map):
+    u a contiguous float64 CUDA tensor (5, E, n^3) of 3D Euler states, M
+    (n + 2, n), post_map "entropy" (conserved -> entropy variables) or
+    "conserved" (the map back); out (5, E, (n + 2)^3), not overlapping u."""
+    import torch
+    if post_map not in POST_MAP:
+        raise ValueError(f"post_map must be one of {sorted(POST_MAP)}")
+    if not isinstance(u, torch.Tensor) or u.device.type != "cuda" or u.dtype != torch.float64:
+        raise TypeError("u must be a float64 CUDA tensor")
+    if not u.is_contiguous() or u.dim() != 3 or u.shape[0] != 5 or u.shape[2] != n ** 3:
+        raise ValueError(f"u must be a contiguous (5, E, {n ** 3}) tensor, got {tuple(u.shape)}")
+    Mh = np.ascontiguousarray(M, dtype=np.float64)
+    if Mh.ndim != 2 or Mh.shape[1] != n:
+        raise ValueError(f"M must be (n_out, {n})")
+    n_out = Mh.shape[0]
+    shape = (5, u.shape[1], n_out ** 3)
+    if out is None:
+        out = torch.empty(shape, dtype=u.dtype, device=u.device)
+    elif tuple(out.shape) != shape or out.dtype != u.dtype or not out.is_contiguous() or out.device != u.device:
+        raise ValueError(f"out must be a contiguous float64 tensor {shape} on u's device")
+    check(lib().sf_tensor_apply_rect_map(u.data_ptr(), u.shape[1], n, n_out, POST_MAP[post_map], float(gamma),
+                                         Mh.ctypes.data_as(_dp), out.data_ptr(), _stream_handle(stream)),
+          "sf_tensor_apply_rect_map")
     _record(stream, u, out)
     return out
 

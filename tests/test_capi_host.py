@@ -272,6 +272,30 @@ def test_tensor_rect_validation(sf):
     assert L.sf_basis_rect(4, 17, 0, None, None) == -2
 
 
+def test_tensor_rect_map_validation(sf):
+    """sf_tensor_apply_rect_map rejects, before any HIP call, every request
+    outside its contract (map kind, gamma, sizes, overlap, M)."""
+    L = sf.lib()
+    M = np.ones((10, 8))
+    Mp = M.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    f = L.sf_tensor_apply_rect_map
+    big = 10 ** 9
+    assert f(BAD, 4, 8, 10, 0, 1.4, Mp, BAD + big, None) == -1     # SF_MAP_NONE is no fused map
+    assert f(BAD, 4, 8, 10, 3, 1.4, Mp, BAD + big, None) == -1     # unknown map
+    assert f(BAD, 4, 8, 10, 1, 1.0, Mp, BAD + big, None) == -1     # gamma must exceed 1
+    assert f(BAD, 4, 8, 10, 1, float("nan"), Mp, BAD + big, None) == -1
+    assert f(BAD, -1, 8, 10, 1, 1.4, Mp, BAD + big, None) == -1    # E < 0
+    assert f(BAD, 4, 8, 10, 1, 1.4, None, BAD + big, None) == -1   # null M
+    assert f(BAD, 4, 8, 8, 1, 1.4, Mp, BAD + big, None) == -2      # n_out != n_in + 2
+    assert f(BAD, 4, 9, 11, 2, 1.4, Mp, BAD + big, None) == -2     # n_in > 8
+    assert f(BAD, 4, 8, 10, 1, 1.4, Mp, BAD, None) == -1           # out overlaps in
+    assert f(None, 4, 8, 10, 2, 1.4, Mp, BAD + big, None) == -1    # null in
+    M[0, 0] = np.inf
+    assert f(BAD, 4, 8, 10, 1, 1.4, Mp, BAD + big, None) == -1     # non-finite M
+    M[0, 0] = 1.0
+    assert f(None, 0, 8, 10, 1, 1.4, Mp, None, None) == 0          # E = 0
+
+
 def test_missing_library_fails_loudly(tmp_path):
     """Without libsfhad.so every binding call raises: there is no CPU
     fallback (checked in a fresh interpreter with the library path pointed

@@ -114,3 +114,40 @@ def test_uncollocated_collocated_limit(torch_dev, sf, orc):
     rh = sf.tensor_apply(y, n, 3, np.ascontiguousarray(V.T)).cpu().numpy()
     ref = orc.tensor_apply(orc.dense_volume(u.cpu().numpy(), n, 3, "euler"), n, 3, V.T)
     assert relerr(rh, ref) <= TOL
+
+
+def map_block_elements(n):
+    """Elements per block of the fused interpolation + map (the rectangular
+    kernel's slabs per block for n -> n + 2, rounded down to whole elements):
+    used to size the inputs so that several blocks and a ragged last one run."""
+    mx = n + 2
+    stage = 6144
+    g = max(1, min(stage // mx ** 3, 512 // mx ** 2))
+    return max(1, g // 5)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 6, 7, 8])
+def test_fused_interpolation_and_map(torch_dev, sf, orc, n):
+    """sf_tensor_apply_rect_map (interpolation to n + 2 nodes and the
+    pointwise map in one pass) against the two separate calls -- the same
+    bits, since the map is the same code -- and against the oracle, for both
+    maps of the uncollocated path: v(V u_hat) and u(V P v)."""
+    torch = torch_dev
+    m = n + 2
+    E = 3 * map_block_elements(n) + 1
+    uh = modal_state(orc, E, n, seed=300 + n)
+    V, P = sf.basis_rect(n, m, "gl")
+    x = torch.from_numpy(uh).cuda()
+    vq_two = sf.entropy_variables(sf.tensor_apply(x, n, 3, V))
+    vq = sf.tensor_apply_map(x, n, V, "entropy")
+    wh = sf.tensor_apply(vq, m, 3, P)                          # modes of the entropy variables
+    ut_two = sf.conserved_variables(sf.tensor_apply(wh, n, 3, V))
+    ut = sf.tensor_apply_map(wh, n, V, "conserved")
+    torch.cuda.synchronize()
+    assert torch.equal(vq, vq_two) and torch.equal(ut, ut_two)
+    vq_o = pointwise(orc.entropy_vars, orc.tensor_apply(uh, n, 3, V))
+    ut_o = pointwise(orc.conserved_from_entropy, orc.tensor_apply(orc.tensor_apply(vq_o, m, 3, P), n, 3, V))
+    assert relerr(vq.cpu().numpy(), vq_o) <= TOL
+    err = relerr(ut.cpu().numpy(), ut_o)
+    print(f"fused n={n} -> {m}: entropy-projected state error {err:.2e}")
+    assert err <= TOL
