@@ -272,14 +272,17 @@ typedef enum {
 /* sf_tensor_apply_rect followed by a pointwise map of every output node, in
  * one pass: out = map((M (x) M (x) M) in) for the 5 variables of each of the
  * elem_count elements (d = 3, nvar = 5 implied; layouts as above).  The
- * interpolation steps of the uncollocated modal path, to the n + 2 quadrature
- * nodes of the over-integration (the proof of Theorem 1): u_q = V u_hat with
- * v(u_q), and u(V P v) with the map back.  The map is the same code as the
- * separate map calls, so the result is the same as sf_tensor_apply_rect then
- * sf_entropy_variables (or sf_conserved_variables), bit for bit, without
- * writing and re-reading the intermediate array.
+ * steps of the uncollocated modal path that end on the quadrature nodes of
+ * the over-integration (the proof of Theorem 1): u_q = V u_hat with v(u_q)
+ * (n -> n + 2), and the entropy projection u(V P v) with the map back,
+ * either as V applied to P v (n -> n + 2) or as the projection V P applied
+ * on the quadrature nodes (m -> m).  The map is the same code as the
+ * separate map calls: for n_out = n_in + 2 the result is that of
+ * sf_tensor_apply_rect then sf_entropy_variables (or sf_conserved_variables)
+ * bit for bit, without writing and re-reading the intermediate array.
  *   map       SF_MAP_ENTROPY_VARIABLES or SF_MAP_CONSERVED_VARIABLES
- *   n_out     n_in + 2 with 3 <= n_in <= 8 (else SF_ERR_UNSUPPORTED)
+ *   n_out     n_in + 2 with 3 <= n_in <= 8, or n_in with 3 <= n_in <= 10
+ *             (else SF_ERR_UNSUPPORTED)
  *   gamma     > 1 (the ratio of specific heats of the map)
  *   out       must not overlap in.
  * States must be physical (rho > 0, p > 0 after the interpolation; -v_4 > 0

@@ -340,8 +340,10 @@ int sf_tensor_apply_rect_map(const double *in, int64_t E, int n_in, int n_out, i
     if (!(gamma > 1.0) || !std::isfinite(gamma)) return fail(SF_ERR_ARG, "gamma must be finite and > 1");
     if (E < 0) return fail(SF_ERR_ARG, "elem_count must be >= 0");
     if (!M_host) return fail(SF_ERR_ARG, "null M_host");
-    if (n_in < 3 || n_in > 8 || n_out != n_in + 2)
-        return fail(SF_ERR_UNSUPPORTED, "the fused map is built for n_in in [3, 8] and n_out = n_in + 2");
+    const bool up = n_out == n_in + 2 && n_in >= 3 && n_in <= 8, sq = n_out == n_in && n_in >= 3 && n_in <= 10;
+    if (!(up || sq))
+        return fail(SF_ERR_UNSUPPORTED,
+                    "the fused map is built for n_out = n_in + 2 (n_in in [3, 8]) or n_out = n_in (n_in in [3, 10])");
     for (int i = 0; i < n_in * n_out; ++i)
         if (!std::isfinite(M_host[i])) return fail(SF_ERR_ARG, "M_host has a non-finite entry");
     const int64_t NI = ipow(n_in, 3), NO = ipow(n_out, 3);

@@ -256,7 +256,7 @@ __host__ __device__ constexpr int rect_map_slabs_per_block(int ni, int no) {
 // NI, NO > 0: the sizes as compile-time constants (every index split and
 // product folds into shifts and constant multiplies); 0: run-time sizes
 // from the arguments.  The code is the same.  MAP != 0 (3D Euler, 5
-// variables, interpolation to more nodes): a block takes the 5 variable
+// variables, n_out = n_in + 2 or n_out = n_in): a block takes the 5 variable
 // slabs of whole elements, keeps the last pass in LDS and applies a
 // pointwise map to each output node before the store -- conserved to
 // entropy variables (MAP = 1) or back (MAP = 2) -- so the map costs no
@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(kTensorThreads) tensor_rect_kernel(const RectA
     extern __shared__ double buf[];
     const auto A = kernel_args<RectArgs>();
     constexpr bool CT = NI > 0 && NO > 0;
-    static_assert(MAP == 0 || (CT && DIM == 3 && NI < NO), "the fused map is built for 3D interpolation");
+    static_assert(MAP == 0 || (CT && DIM == 3 && NI <= NO), "the fused map is built for 3D, n_out >= n_in");
     constexpr int MX = NI > NO ? NI : NO;
     const int ni = CT ? NI : A->ni, no = CT ? NO : A->no;
     constexpr int STAGE = CT ? rect_stage(NI, NO) : kRectStage;
@@ -471,17 +471,21 @@ int launch_tensor_rect(const TensorRequest &r) {
     // (n modes <-> n + 2 quadrature nodes, n = 3..8, 3D); run-time otherwise
     const void *fn = nullptr;
     if (r.post_map != SF_MAP_NONE) {
-        // the fused map: interpolation n -> n + 2 (3D, 5 variables) only
-        if (r.d != 3 || r.nvar != 5 || r.n_out != r.n + 2 || r.n < 3 || r.n > 8) {
-            set_error("the fused map is built for 3D Euler states and n -> n + 2 nodes, n = 3..8");
+        // the fused map: 3D, 5 variables, n -> n + 2 (n = 3..8) or n -> n
+        // (n = 3..10, e.g. the projection V P on the quadrature nodes)
+        const bool up = r.n_out == r.n + 2 && r.n >= 3 && r.n <= 8, sq = r.n_out == r.n && r.n >= 3 && r.n <= 10;
+        if (r.d != 3 || r.nvar != 5 || !(up || sq)) {
+            set_error("the fused map is built for 3D Euler states, n -> n + 2 (n = 3..8) or n -> n (n = 3..10)");
             return SF_ERR_UNSUPPORTED;
         }
 #define SF_RECT_MAP(NI_, NO_)                                                                              \
-        if (r.n == NI_)                                                                                    \
+        if (r.n == NI_ && r.n_out == NO_)                                                                  \
             fn = r.post_map == SF_MAP_ENTROPY_VARIABLES                                                    \
                      ? reinterpret_cast<const void *>(&tensor_rect_kernel<3, NI_, NO_, SF_MAP_ENTROPY_VARIABLES>) \
                      : reinterpret_cast<const void *>(&tensor_rect_kernel<3, NI_, NO_, SF_MAP_CONSERVED_VARIABLES>);
         SF_RECT_MAP(3, 5) SF_RECT_MAP(4, 6) SF_RECT_MAP(5, 7) SF_RECT_MAP(6, 8) SF_RECT_MAP(7, 9) SF_RECT_MAP(8, 10)
+        SF_RECT_MAP(3, 3) SF_RECT_MAP(4, 4) SF_RECT_MAP(5, 5) SF_RECT_MAP(6, 6) SF_RECT_MAP(7, 7) SF_RECT_MAP(8, 8)
+        SF_RECT_MAP(9, 9) SF_RECT_MAP(10, 10)
 #undef SF_RECT_MAP
         a.G = rect_map_slabs_per_block(r.n, r.n_out);
     } else {

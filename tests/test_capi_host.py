@@ -286,7 +286,8 @@ def test_tensor_rect_map_validation(sf):
     assert f(BAD, 4, 8, 10, 1, float("nan"), Mp, BAD + big, None) == -1
     assert f(BAD, -1, 8, 10, 1, 1.4, Mp, BAD + big, None) == -1    # E < 0
     assert f(BAD, 4, 8, 10, 1, 1.4, None, BAD + big, None) == -1   # null M
-    assert f(BAD, 4, 8, 8, 1, 1.4, Mp, BAD + big, None) == -2      # n_out != n_in + 2
+    assert f(BAD, 4, 8, 9, 1, 1.4, Mp, BAD + big, None) == -2      # n_out neither n_in + 2 nor n_in
+    assert f(BAD, 4, 11, 11, 1, 1.4, Mp, BAD + big, None) == -2    # square beyond n = 10
     assert f(BAD, 4, 9, 11, 2, 1.4, Mp, BAD + big, None) == -2     # n_in > 8
     assert f(BAD, 4, 8, 10, 1, 1.4, Mp, BAD, None) == -1           # out overlaps in
     assert f(None, 4, 8, 10, 2, 1.4, Mp, BAD + big, None) == -1    # null in

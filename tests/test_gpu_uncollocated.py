@@ -151,3 +151,34 @@ def test_fused_interpolation_and_map(torch_dev, sf, orc, n):
     err = relerr(ut.cpu().numpy(), ut_o)
     print(f"fused n={n} -> {m}: entropy-projected state error {err:.2e}")
     assert err <= TOL
+
+
+@pytest.mark.parametrize("m", [3, 5, 7, 8, 10])
+def test_fused_projection_and_map(torch_dev, sf, orc, m):
+    """The entropy projection as one operator on the quadrature nodes,
+    u(Pi v) with Pi = V P (m x m, n = m - 2 modes; m = 3 takes Pi = I), fused
+    with the map back in one pass (sf_tensor_apply_rect_map with
+    n_out = n_in): against the oracle, and against the square transformation
+    followed by the separate map (the two kernels tile the contraction
+    differently, so to rounding, not bit for bit)."""
+    torch = torch_dev
+    n = max(m - 2, 2)
+    mx = m
+    G = max(1, min(6144 // mx ** 3, 512 // mx ** 2)) // 5
+    E = 3 * max(G, 1) + 1
+    uq = orc.tensor_apply(modal_state(orc, E, m, seed=400 + m), m, 3, sf.basis_rect(m, m, "gl")[0])
+    if m > 3:
+        V, P = sf.basis_rect(n, m, "gl")
+        Pi = V @ P
+    else:
+        Pi = np.eye(m)
+    v = pointwise(orc.entropy_vars, uq)
+    x = torch.from_numpy(np.ascontiguousarray(v)).cuda()
+    ut = sf.tensor_apply_map(x, m, Pi, "conserved")
+    ut_two = sf.conserved_variables(sf.tensor_apply(x, m, 3, Pi))
+    torch.cuda.synchronize()
+    ref = pointwise(orc.conserved_from_entropy, orc.tensor_apply(v, m, 3, Pi))
+    err = relerr(ut.cpu().numpy(), ref)
+    print(f"fused projection m={m}: {err:.2e}")
+    assert err <= TOL
+    assert relerr(ut.cpu().numpy(), ut_two.cpu().numpy()) <= 1e-14
