@@ -123,18 +123,26 @@ struct Geom {
 // (n = 5 with 5 elements, n = 6 with 3, n = 7 with 2, n = 10 with 1) ran as
 // if only one block fitted per CU, and bounding registers below the natural
 // count (spilling) was slower, so n = 7 and 11 stay grouped.
+// With one element per block the reference values of the staging step can be
+// derived by every thread instead of through LDS and a barrier: 1.03x at
+// n = 8 and 1.01x at n = 12, 13 (FP64); it costs the registers that hold them
+// while the stage runs, which made n = 9 spill more (no gain), the FP32-split
+// form at n = 9 drop to 3 waves per SIMD (0.87x) and the pressure-fix flux at
+// n = 8 exceed 168 VGPRs (0.71x), so those keep the LDS form.
 struct VolumeShape {
     int fe;
     int min_waves;
     bool ahead;
+    bool own_ref;
 };
-constexpr VolumeShape euler_volume_shape(int n, bool fp64) {
-    return n == 5 ? VolumeShape{fp64 ? 3 : 0, 1, false}
-         : n == 6 ? VolumeShape{2, 1, true}
-         : n == 9 ? VolumeShape{1, fp64 ? 3 : 1, false}
-         : n == 10 ? VolumeShape{2, 1, false}
-         : (n == 12 || n == 13) ? VolumeShape{1, 1, false}
-         : VolumeShape{0, 1, n <= 8};
+constexpr VolumeShape euler_volume_shape(int n, bool fp64, bool pfix = false) {
+    return n == 5 ? VolumeShape{fp64 ? 3 : 0, 1, false, false}
+         : n == 6 ? VolumeShape{2, 1, true, false}
+         : n == 9 ? VolumeShape{1, fp64 ? 3 : 1, false, false}
+         : n == 10 ? VolumeShape{2, 1, false, false}
+         : (n == 12 || n == 13) ? VolumeShape{1, 1, false, fp64}
+         : n == 8 ? VolumeShape{0, 1, true, fp64 && !pfix}
+         : VolumeShape{0, 1, n <= 8, false};
 }
 
 // Padded LDS base index and stride of line `line` in direction m
@@ -350,6 +358,7 @@ template <bool PFIX>
 struct EulerFP64T {
     using Real = double;
     static constexpr int NV = 5;
+    static constexpr bool PRESSURE_FIX = PFIX;
     static constexpr int NS = PFIX ? 8 : 7;
     static constexpr int NX = 0;
     static constexpr int NREF = 2;  // 1/rho_0, 1/beta_0

@@ -179,7 +179,7 @@ using VolumeWork = VolumeWorkT<false>;  // serving and curvilinear kernels (regi
 // steps a1..a6 with the line work of `work`.  lds holds SfLayout::LDS_D
 // doubles, sref SfLayout::REF_D.  FE selects the lane mapping (Geom); the
 // flat mapping is built for the volume pairs only.
-template <int N, int DIM, class P, int FE = 0, class Op, class Work = VolumeWork>
+template <int N, int DIM, class P, int FE = 0, bool OWNREF = false, class Op, class Work = VolumeWork>
 __device__ __forceinline__ void sf_block(const double *__restrict__ u, double *__restrict__ out, int64_t E,
                                          int64_t e0, const Op &op, double gamma, double *lds, double *sref,
                                          const Work &work = Work{}, const double *__restrict__ aux = nullptr) {
@@ -197,9 +197,8 @@ __device__ __forceinline__ void sf_block(const double *__restrict__ u, double *_
     const size_t vstride = (size_t)E * G::NODES;
     const size_t gbase = (size_t)e0 * G::NODES;
 
-    // a1: every load of the staging pass is issued before any conversion;
-    // the thread holding an element's first node then derives the element's
-    // reference values from it (one memory round trip for the whole stage)
+    // a1: every load of the staging pass is issued before any conversion
+    // (one memory round trip for the whole stage)
     constexpr int SPT = (G::EPB * G::NODES + G::THREADS - 1) / G::THREADS;  // nodes per thread
     double uc[SPT][P::NV + P::NX];  // conserved variables, then P::NX extra inputs from aux
 #pragma unroll
@@ -212,7 +211,27 @@ __device__ __forceinline__ void sf_block(const double *__restrict__ u, double *_
             for (int x = 0; x < P::NX; ++x) uc[k][P::NV + x] = aux[x * vstride + gbase + i];
         }
     }
-    if (P::NREF > 0) {
+    // OWNREF with one element per block: every thread derives the element's
+    // reference values itself from the element's first node (one address
+    // for all lanes), so the stage needs no barrier of its own (the
+    // standalone volume kernel: 1.03x at n = 8; the registers it keeps live
+    // make the surface and serving kernels spill, so they do not take it).
+    // Otherwise the thread holding an element's first node derives them into
+    // LDS, then a barrier.
+    constexpr bool kOwnRef = OWNREF && G::EPB == 1 && P::NREF > 0;
+    double rloc[NREF];
+    if constexpr (kOwnRef) {
+        double u0[P::NV + P::NX];
+#pragma unroll
+        for (int v = 0; v < P::NV; ++v) u0[v] = u[v * vstride + gbase];
+#pragma unroll
+        for (int x = 0; x < P::NX; ++x) u0[P::NV + x] = aux[x * vstride + gbase];
+        P::make_ref(u0, gamma, rloc);
+        if (tid == 0) {
+#pragma unroll
+            for (int q = 0; q < NREF; ++q) sref[q] = rloc[q];  // for the line work, after the next barrier
+        }
+    } else if (P::NREF > 0) {
 #pragma unroll
         for (int k = 0; k < SPT; ++k) {
             const int i = tid + k * G::THREADS;
@@ -225,7 +244,7 @@ __device__ __forceinline__ void sf_block(const double *__restrict__ u, double *_
         const int i = tid + k * G::THREADS;
         if (i < nvalid) {
             R s[P::NS];
-            P::stage(uc[k], sref + (i / G::NODES) * NREF, gamma, s);
+            P::stage(uc[k], kOwnRef ? rloc : sref + (i / G::NODES) * NREF, gamma, s);
             const int el = i / G::NODES, node = i - el * G::NODES;
             const int li = el * G::PADN + G::pidx(node);
 #pragma unroll

@@ -5,16 +5,22 @@
 #include "sf_block.h"
 
 #include <string>
+#include <type_traits>
 
 namespace sfhad {
 namespace dev {
+
+template <class P, class = void>
+struct PressureFix : std::false_type {};
+template <class P>
+struct PressureFix<P, std::void_t<decltype(P::PRESSURE_FIX)>> : std::bool_constant<P::PRESSURE_FIX> {};
 
 // Launch shape of the standalone kernel: the 3D Euler flux takes
 // euler_volume_shape, the scalar fluxes the grouped mapping.
 template <int N, int DIM, class P>
 constexpr VolumeShape volume_shape() {
-    return (DIM == 3 && P::NV == 5) ? euler_volume_shape(N, sizeof(typename P::Real) == 8)
-                                    : VolumeShape{0, 1, N <= 8};
+    return (DIM == 3 && P::NV == 5) ? euler_volume_shape(N, sizeof(typename P::Real) == 8, PressureFix<P>::value)
+                                    : VolumeShape{0, 1, N <= 8, false};
 }
 
 template <int N, int DIM, class P>
@@ -27,12 +33,13 @@ sf_volume_kernel(const VolArgs<N> args) {
     __shared__ double sref[L::REF_D];
     const int64_t e0 = (int64_t)blockIdx.x * Geom<N, DIM, FE>::EPB;
     using Work = VolumeWorkT<volume_shape<N, DIM, P>().ahead>;
+    constexpr bool OWN = volume_shape<N, DIM, P>().own_ref;
     if constexpr (N <= 9) {
-        sf_block<N, DIM, P, FE>(args.u, args.out, args.E, e0, ParamOp<N>{args.op}, args.gamma, lds, sref,
-                                Work{});
+        sf_block<N, DIM, P, FE, OWN>(args.u, args.out, args.E, e0, ParamOp<N>{args.op}, args.gamma, lds, sref,
+                                     Work{});
     } else {
         const auto A = kernel_args<VolArgs<N>>();
-        sf_block<N, DIM, P, FE>(A->u, A->out, A->E, e0, KernargOp<N>{&A->op}, A->gamma, lds, sref, Work{});
+        sf_block<N, DIM, P, FE, OWN>(A->u, A->out, A->E, e0, KernargOp<N>{&A->op}, A->gamma, lds, sref, Work{});
     }
 }
 
