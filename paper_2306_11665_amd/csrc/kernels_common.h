@@ -74,12 +74,14 @@ __device__ __forceinline__ kernarg_ptr<T> kernel_args() {
 // other over the block's lanes (element, then direction, then line), so
 // that a wave may hold lines of several directions; the flux code then
 // takes the direction as a per-lane value.  The flat mapping fills the
-// lanes when n^(d-1) does not divide into 64 (n = 6, 9, 12, ...).
+// lanes when n^(d-1) does not divide into 64 (n = 6, 9, 12, ...).  FE < 0:
+// the grouped mapping over -FE elements per block (each direction group
+// takes the lines of all of them, the group rounded up to whole waves).
 template <int N, int DIM, int FE = 0>
 struct Geom {
     static constexpr int LINES = DIM == 3 ? N * N : N;       // lines per direction per element
     static constexpr int NODES = LINES * N;                  // n^d
-    static constexpr int EPB = FE > 0 ? FE : (LINES >= 64 ? 1 : 64 / LINES);  // elements per block
+    static constexpr int EPB = FE > 0 ? FE : FE < 0 ? -FE : (LINES >= 64 ? 1 : 64 / LINES);  // elements per block
     static constexpr int LPD = ((EPB * LINES + 63) / 64) * 64;  // lanes per direction group (grouped)
     static constexpr int LANES = FE > 0 ? EPB * DIM * LINES : DIM * LPD;  // lanes with a line (flat: all)
     static constexpr int THREADS = FE > 0 ? ((LANES + 63) / 64) * 64 : DIM * LPD;
@@ -102,7 +104,8 @@ struct Geom {
 };
 
 // Launch shape of the standalone 3D Euler volume kernels: elements per block
-// of the flat mapping (0: the grouped mapping), the minimum number of waves
+// of the flat mapping (0: the grouped mapping; -k: grouped over k elements
+// per block), the minimum number of waves
 // per SIMD the register budget must allow (1: no bound), and whether the
 // next partner node is loaded one pair ahead.  Measured on MI355X (n = 8
 // state regrouped into n^3-node elements, against the grouped mapping):
@@ -113,10 +116,15 @@ struct Geom {
 //           1.22x FP32-split;
 //   n = 9:  one element per 4-wave block (243/256, grouped 81/128), FP64 held
 //           to 3 waves per SIMD: 2.0x;
-//   n = 10: two elements per 10-wave block (600/640 lanes, 124 KB of LDS: one
-//           block per CU, 10 waves, where the grouped 6-wave block of one
-//           element left 6): 1.19x FP64 (168 VGPRs, 52 bytes spilled),
-//           1.28x FP32-split, 1.18x pressure fix;
+//   n = 10: two elements per block (124 KB of LDS: one block per CU) in the
+//           grouped mapping, 3 directions x 4 waves (600 of 768 lanes): a
+//           flat 10-wave block of the two (600/640) ran 1.19x FP64, 1.28x
+//           FP32-split and 1.18x pressure fix against the grouped 6-wave
+//           block of one element, but puts 3 waves on two SIMDs and 2 on
+//           the others; the 12-wave grouped block runs 3 on each, with the
+//           direction a constant per wave (32 instead of 52 bytes spilled
+//           at 168 VGPRs): 1.10x FP64 and pressure fix, 1.04x FP32-split
+//           over the flat block;
 //   n = 12, 13: one element per 7- and 8-wave block (432/448, 507/512): 1.5x
 //           and 1.6x (the grouped 9-wave blocks had to spill to fit).
 // n = 2, 3, 4, 8 fill their waves grouped.  Flat blocks of 5 or 6 waves
@@ -139,7 +147,7 @@ constexpr VolumeShape euler_volume_shape(int n, bool fp64, bool pfix = false) {
     return n == 5 ? VolumeShape{fp64 ? 3 : 0, 1, false, false}
          : n == 6 ? VolumeShape{2, 1, true, false}
          : n == 9 ? VolumeShape{1, fp64 ? 3 : 1, false, false}
-         : n == 10 ? VolumeShape{2, 1, false, false}
+         : n == 10 ? VolumeShape{-2, 1, false, false}
          : (n == 12 || n == 13) ? VolumeShape{1, 1, false, fp64}
          : n == 8 ? VolumeShape{0, 1, true, fp64 && !pfix}
          : VolumeShape{0, 1, n <= 8, false};

@@ -6,7 +6,8 @@
 // One workgroup per block of EPB elements, one line per lane.  Grouped
 // mapping (FE = 0): d groups of LPD lanes, group m handling every line of
 // direction m of the block's elements (at n = 8 in 3D: one element, 3 waves
-// of 64 lanes, 64 lines each).  Flat mapping (FE > 0 elements per block):
+// of 64 lanes, 64 lines each; FE < 0: the same over -FE elements per
+// block).  Flat mapping (FE > 0 elements per block):
 // the lines of all directions laid out one after the other over the lanes,
 // the direction a per-lane value (Geom).
 //
