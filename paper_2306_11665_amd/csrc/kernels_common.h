@@ -125,12 +125,17 @@ struct Geom {
 //           direction a constant per wave (32 instead of 52 bytes spilled
 //           at 168 VGPRs): 1.10x FP64 and pressure fix, 1.04x FP32-split
 //           over the flat block;
+//   n = 11: FP32-split two elements per grouped 12-wave block (726/768; 118
+//           KB of LDS, 3 waves on every SIMD) against one per 6-wave block:
+//           1.22x; FP64 stays at one (186 VGPRs; held to 168 so that two
+//           82 KB blocks could share a CU, it spilled and ran 0.88x);
 //   n = 12, 13: one element per 7- and 8-wave block (432/448, 507/512): 1.5x
 //           and 1.6x (the grouped 9-wave blocks had to spill to fit).
 // n = 2, 3, 4, 8 fill their waves grouped.  Flat blocks of 5 or 6 waves
 // (n = 5 with 5 elements, n = 6 with 3, n = 7 with 2, n = 10 with 1) ran as
 // if only one block fitted per CU, and bounding registers below the natural
-// count (spilling) was slower, so n = 7 and 11 stay grouped.
+// count (spilling) was slower, so n = 7 and FP64 n = 11 stay grouped over
+// one element.
 // With one element per block the reference values of the staging step can be
 // derived by every thread instead of through LDS and a barrier: 1.03x at
 // n = 8 and 1.01x at n = 12, 13 (FP64); it costs the registers that hold them
@@ -148,6 +153,7 @@ constexpr VolumeShape euler_volume_shape(int n, bool fp64, bool pfix = false) {
          : n == 6 ? VolumeShape{2, 1, true, false}
          : n == 9 ? VolumeShape{1, fp64 ? 3 : 1, false, false}
          : n == 10 ? VolumeShape{-2, 1, false, false}
+         : n == 11 ? VolumeShape{fp64 ? 0 : -2, 1, false, false}
          : (n == 12 || n == 13) ? VolumeShape{1, 1, false, fp64}
          : n == 8 ? VolumeShape{0, 1, true, fp64 && !pfix}
          : VolumeShape{0, 1, n <= 8, false};
