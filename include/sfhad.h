@@ -318,6 +318,14 @@ const char *sf_version(void);
  * `stream` (a hipStream_t, NULL for the null stream).  For tests. */
 int sf_diag_log1p(const double *x, int64_t n, double *y, void *stream);
 
+/* Diagnostics: y[i] = ln x[i] and y[i] = e^x[i] as the entropy-variable maps
+ * compute them (sf_entropy_variables, sf_conserved_variables, sf_entropy_trace
+ * and the fused maps of sf_tensor_apply_rect_map).  Same arguments and errors
+ * as sf_diag_log1p; any x (ln: -inf at 0, NaN below 0; exp: 0 and +inf beyond
+ * the double range).  For tests. */
+int sf_diag_log(const double *x, int64_t n, double *y, void *stream);
+int sf_diag_exp(const double *x, int64_t n, double *y, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of residual-evaluation requests over          */
 /* device-resident meshes of mixed n (one GPU).                               */

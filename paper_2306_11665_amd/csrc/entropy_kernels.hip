@@ -13,10 +13,10 @@
 // One workgroup per element: the nodal entropy variables go to LDS (one
 // padded array per component), then each thread takes facet nodes in the
 // output order (face-major, t fastest: coalesced stores) and interpolates
-// along its line.  Moves 8 B x 5 x (n^3 + 6 n^2) per element; the logarithms
-// and exponentials (ocml, full FP64 accuracy) make it about as much VALU- as
-// HBM-bound.  Quotients are products with a refined reciprocal (about one
-// ulp), the 1/(gamma - 1) factors one reciprocal per thread.
+// along its line.  Moves 8 B x 5 x (n^3 + 6 n^2) per element; the maps are
+// the shared ones of entropy_maps.h (own logarithm and exponential, about one
+// ulp; quotients are products with a refined reciprocal), the 1/(gamma - 1)
+// factors one reciprocal per thread.
 #include "entropy_maps.h"
 #include "kernels_common.h"
 #include "sfhad_internal.h"
@@ -70,19 +70,11 @@ __global__ void __launch_bounds__(kTraceThreads) entropy_trace_kernel(const Trac
     for (int j = 0; j < NPT; ++j) {
         const int i = tid + j * kTraceThreads;
         if (i >= NODES) break;
-        const double rho = uc[j][0];
-        const double irho = rcp_fine(rho);
-        const double vx = uc[j][1] * irho, vy = uc[j][2] * irho, vz = uc[j][3] * irho;
-        const double q = vx * vx + vy * vy + vz * vz;
-        const double p = (g - 1.0) * (uc[j][4] - 0.5 * rho * q);
-        const double rp = rho * rcp_fine(p);
-        const double s = log(p) - g * log(rho);
+        double y[5];
+        entropy_from_conserved(uc[j], g, igm1, y);
         const int li = i + i / N;
-        sv[li] = (g - s) * igm1 - 0.5 * rp * q;
-        sv[PAD + li] = rp * vx;
-        sv[2 * PAD + li] = rp * vy;
-        sv[3 * PAD + li] = rp * vz;
-        sv[4 * PAD + li] = -rp;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) sv[c * PAD + li] = y[c];
     }
     __syncthreads();
     const size_t fs = (size_t)A->E * NF * T;
@@ -99,18 +91,10 @@ __global__ void __launch_bounds__(kTraceThreads) entropy_trace_kernel(const Trac
 #pragma unroll
             for (int c = 0; c < 5; ++c) v[c] = __builtin_fma(l, sv[c * PAD + li], v[c]);
         }
-        const double rp = -v[4];
-        const double irp = rcp_fine(rp);
-        const double vx = v[1] * irp, vy = v[2] * irp, vz = v[3] * irp;
-        const double q = vx * vx + vy * vy + vz * vz;
-        const double s = g - (g - 1.0) * (v[0] + 0.5 * rp * q);
-        const double rho = exp(-(s + log(rp)) * igm1);
-        const double p = rho * irp;
-        A->uf[fbase + j] = rho;
-        A->uf[fs + fbase + j] = rho * vx;
-        A->uf[2 * fs + fbase + j] = rho * vy;
-        A->uf[3 * fs + fbase + j] = rho * vz;
-        A->uf[4 * fs + fbase + j] = p * igm1 + 0.5 * rho * q;
+        double y[5];
+        conserved_from_entropy(v, g, igm1, y);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) A->uf[c * fs + fbase + j] = y[c];
     }
 }
 

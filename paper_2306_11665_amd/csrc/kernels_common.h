@@ -273,6 +273,45 @@ __device__ __forceinline__ double log_ratio(double x, double ix0) {
     return log_core<false>(q, e);
 }
 
+// ln x: ln(x + 0) as above for a positive normal x, about one ulp; -inf at
+// 0, +inf at +inf and NaN below 0 or at NaN (selects, no branch).
+__device__ __forceinline__ double log_pos(double x) {
+    const double r = log_core<false>(x, 0.0);
+    const double inf = __builtin_inf();
+    return (x > 0.0 && x < inf) ? r : (x == 0.0 ? -inf : (x == inf ? inf : __builtin_nan("")));
+}
+
+// e^x to about one ulp without a library call (Cody and Waite's reduction):
+// x = k ln 2 + r with k = rint(x / ln 2) and r taken in two steps with the
+// split ln 2 above (k kLn2Hi is exact for |k| < 2^11, so x is first clamped
+// to [-1400, 1400], beyond which e^x is 0 or +inf in double; NaN passes),
+// |r| <= ln 2 / 2 + ulp; e^r - 1 = r + r^2 P(r), P the Taylor series
+// sum_{j >= 2} r^(j-2) / j! through j = 13 (the first term left out,
+// r^14 / 14!, is below 5e-18), so that 1 + (e^r - 1) rounds once; e^x =
+// 2^k e^r by an exact scaling, which rounds results beyond the double range
+// to +inf or 0.
+constexpr double kInvLn2 = 1.4426950408889634;
+__device__ __forceinline__ double exp_fine(double x) {
+    x = x < -1400.0 ? -1400.0 : (x > 1400.0 ? 1400.0 : x);
+    const double kd = __builtin_rint(x * kInvLn2);
+    double r = __builtin_fma(-kd, kLn2Hi, x);
+    r = __builtin_fma(-kd, kLn2Lo, r);
+    double P = 1.0 / 6227020800.0;                  // 1/13!
+    P = __builtin_fma(P, r, 1.0 / 479001600.0);     // 1/12!
+    P = __builtin_fma(P, r, 1.0 / 39916800.0);      // 1/11!
+    P = __builtin_fma(P, r, 1.0 / 3628800.0);       // 1/10!
+    P = __builtin_fma(P, r, 1.0 / 362880.0);        // 1/9!
+    P = __builtin_fma(P, r, 1.0 / 40320.0);         // 1/8!
+    P = __builtin_fma(P, r, 1.0 / 5040.0);          // 1/7!
+    P = __builtin_fma(P, r, 1.0 / 720.0);           // 1/6!
+    P = __builtin_fma(P, r, 1.0 / 120.0);           // 1/5!
+    P = __builtin_fma(P, r, 1.0 / 24.0);            // 1/4!
+    P = __builtin_fma(P, r, 1.0 / 6.0);             // 1/3!
+    P = __builtin_fma(P, r, 0.5);                   // 1/2!
+    const double em1 = __builtin_fma(r * r, P, r);  // e^r - 1
+    return __builtin_amdgcn_ldexp(1.0 + em1, (int)kd);
+}
+
 // ---------------------------------------------------------------------------
 // Scalar fluxes (1 variable, one stored quantity per node).
 // ---------------------------------------------------------------------------

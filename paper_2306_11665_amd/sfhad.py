@@ -104,8 +104,9 @@ def lib() -> ctypes.CDLL:
         L.sf_tensor_apply_rect_map.restype = ci
         L.sf_basis_rect.argtypes = [ci, ci, ci, _dp, _dp]
         L.sf_basis_rect.restype = ci
-        L.sf_diag_log1p.argtypes = [vp, i64, vp, vp]
-        L.sf_diag_log1p.restype = ci
+        for name in ("sf_diag_log1p", "sf_diag_log", "sf_diag_exp"):
+            getattr(L, name).argtypes = [vp, i64, vp, vp]
+            getattr(L, name).restype = ci
         L.sf_server_destroy.argtypes = [vp]
         L.sf_server_destroy.restype = ci
         _lib = L
@@ -392,16 +393,30 @@ def tensor_apply_map(u, n: int, M, post_map: str, *, gamma=1.4, out=None, stream
     return out
 
 
-def diag_log1p(x, stream=None):
-    """ln(1 + x) by the kernels' staging routine (float64 CUDA tensor in and out)."""
+def _diag(name, x, stream):
     import torch
     if not isinstance(x, torch.Tensor) or x.device.type != "cuda" or x.dtype != torch.float64:
         raise TypeError("x must be a float64 CUDA tensor")
     x = x.contiguous()
     y = torch.empty_like(x)
-    check(lib().sf_diag_log1p(x.data_ptr(), x.numel(), y.data_ptr(), _stream_handle(stream)), "sf_diag_log1p")
+    check(getattr(lib(), name)(x.data_ptr(), x.numel(), y.data_ptr(), _stream_handle(stream)), name)
     _record(stream, x, y)
     return y
+
+
+def diag_log1p(x, stream=None):
+    """ln(1 + x) by the kernels' staging routine (float64 CUDA tensor in and out)."""
+    return _diag("sf_diag_log1p", x, stream)
+
+
+def diag_log(x, stream=None):
+    """ln x by the entropy-variable maps' routine (float64 CUDA tensor in and out)."""
+    return _diag("sf_diag_log", x, stream)
+
+
+def diag_exp(x, stream=None):
+    """e^x by the entropy-variable maps' routine (float64 CUDA tensor in and out)."""
+    return _diag("sf_diag_exp", x, stream)
 
 
 def volume_raw(u_ptr: int, E: int, n: int, d: int, flux: int, out_ptr: int) -> int:

@@ -333,6 +333,45 @@ def test_staging_log1p_accuracy(torch_dev, sf):
     print("log1p worst error / tolerance", worst)
 
 
+def test_map_log_exp_accuracy(torch_dev, sf):
+    """The logarithm and exponential of the entropy-variable maps against
+    mpmath (40 digits): within 2 ulp of the result over the double range
+    (1 ulp of the smallest subnormal more where e^x is subnormal), and the
+    special values: ln 0 = -inf, ln of a negative or NaN = NaN, ln inf = inf,
+    e^x = 0 or inf beyond the range, e^(+-inf) = inf, 0, e^NaN = NaN."""
+    import mpmath as mp
+    torch = torch_dev
+    mp.mp.dps = 40
+    rng = np.random.default_rng(1200)
+    tiny = 2.2250738585072014e-308
+    xl = np.concatenate([rng.uniform(1e-3, 10.0, 2000), 10.0 ** rng.uniform(-307, 308, 2000),
+                         1.0 + rng.uniform(-1e-6, 1e-6, 500), rng.uniform(0.5, 2.0, 1000),
+                         [1.0, 2.0, 0.5, np.nextafter(1.0, 2.0), np.nextafter(1.0, 0.0), tiny,
+                          1.7976931348623157e308]])
+    yl = sf.diag_log(torch.from_numpy(xl).cuda()).cpu().numpy()
+    for xi, yi in zip(xl, yl):
+        ref = mp.log(mp.mpf(float(xi)))
+        assert abs(mp.mpf(float(yi)) - ref) <= 2 * np.spacing(abs(float(ref))), (xi, yi, float(ref))
+    assert yl[-7] == 0.0
+    xe = np.concatenate([rng.uniform(-700.0, 700.0, 3000), rng.uniform(-1.0, 1.0, 1000),
+                         rng.uniform(-1e-10, 1e-10, 200), rng.uniform(-745.0, -708.5, 200),
+                         [0.0, 1.0, -1.0, 709.78, -708.39]])
+    ye = sf.diag_exp(torch.from_numpy(xe).cuda()).cpu().numpy()
+    for xi, yi in zip(xe, ye):
+        ref = mp.exp(mp.mpf(float(xi)))
+        tol = 2 * np.spacing(float(ref)) + (5e-324 if float(ref) < tiny else 0.0)
+        assert abs(mp.mpf(float(yi)) - ref) <= tol, (xi, yi, float(ref))
+    assert ye[-5] == 1.0
+    inf, nan = np.inf, np.nan
+    sl = sf.diag_log(torch.tensor([0.0, -0.0, -1.0, -inf, inf, nan], dtype=torch.float64).cuda()).cpu().numpy()
+    assert sl[0] == -inf and sl[1] == -inf and np.isnan(sl[2]) and np.isnan(sl[3])
+    assert sl[4] == inf and np.isnan(sl[5])
+    se = sf.diag_exp(torch.tensor([710.0, -746.0, 1e300, -1e300, inf, -inf, nan],
+                                  dtype=torch.float64).cuda()).cpu().numpy()
+    assert se[0] == inf and se[1] == 0.0 and se[2] == inf and se[3] == 0.0
+    assert se[4] == inf and se[5] == 0.0 and np.isnan(se[6])
+
+
 def test_library_is_the_path(torch_dev, sf):
     """The product path runs the in-tree HIP library, nothing else."""
     import ctypes
