@@ -214,7 +214,8 @@ constexpr int kRectStage = 4096;  // LDS doubles per block for the slabs (plus p
 // The same for the compile-time size pairs, from A/B runs on MI355X against
 // 4096: 6144 (more slabs per block) ran 1.03-1.17x faster for every pair
 // measured (3 -> 5 up to 9 -> 7) but the projection from 10^3 nodes, which
-// ran faster with fewer (3072: 1.07x at 10 -> 8; 6144: 0.93x).
+// ran faster with fewer (3072: 1.07x at 10 -> 8; 6144: 0.93x; 2048: 0.92x
+// of 3072).
 __host__ __device__ constexpr int rect_stage(int ni, int no) {
     return (ni > no && ni * ni * ni >= 1000) ? 3072 : 6144;
 }
