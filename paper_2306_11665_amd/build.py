@@ -31,14 +31,15 @@ COMMON = [
 ]
 
 # Per-file code generation options, from interleaved A/B runs on MI355X: the
-# volume and serving kernels are scheduled with LLVM's iterative ILP strategy
-# (volume: 1.015-1.033x over the default scheduler for every FP64 form
-# measured, n = 7..12 and the pressure fix, FP32-split unchanged, fewer spills
-# at n = 9, 10; serving: 1.02x FP64 burst throughput).  The other files keep
-# the default: it ran the transformation and entropy kernels 0.99-1.01x, and
+# volume, serving and curvilinear kernels are scheduled with LLVM's iterative
+# ILP strategy (volume: 1.015-1.033x over the default scheduler for every FP64
+# form measured, n = 7..12 and the pressure fix, FP32-split unchanged, fewer
+# spills at n = 9, 10; serving: 1.02x FP64 burst throughput; curvilinear:
+# 1.04x at n = 8, 1.01-1.03x at n = 4, 6, 10).  The other files keep the
+# default: it ran the transformation and entropy kernels 0.99-1.01x, and
 # crashes the compiler on the surface and dense kernels' sources.
 _ILP = ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]
-EXTRA = {"volume_kernels.hip": _ILP, "serve_kernels.hip": _ILP}
+EXTRA = {"volume_kernels.hip": _ILP, "serve_kernels.hip": _ILP, "curv_kernels.hip": _ILP}
 
 
 def _compile(src: str) -> str:

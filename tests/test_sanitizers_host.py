@@ -17,8 +17,8 @@ CSRC = os.path.join(ROOT, "paper_2306_11665_amd", "csrc")
 OBJ = os.path.join(ROOT, "_build", "sfhad")
 ROCM = "/opt/rocm"
 HOST_SOURCES = ["capi.cpp", "operators.cpp", "server.cpp"]
-DEVICE_OBJECTS = ["dense_kernels", "diag_kernels", "entropy_kernels", "surface_kernels", "tensor_kernels",
-                  "serve_kernels", "volume_kernels"]
+DEVICE_OBJECTS = ["dense_kernels", "diag_kernels", "entropy_kernels", "surface_kernels", "curv_kernels",
+                  "tensor_kernels", "serve_kernels", "volume_kernels"]
 DRIVER = os.path.join(ROOT, "tests", "c_client", "sfhad_host_sanitized.c")
 
 
