@@ -273,8 +273,9 @@ __device__ __forceinline__ double log_ratio(double x, double ix0) {
     return log_core<false>(q, e);
 }
 
-// ln x: ln(x + 0) as above for a positive normal x, about one ulp; -inf at
-// 0, +inf at +inf and NaN below 0 or at NaN (selects, no branch).
+// ln x: ln(x + 0) as above for a positive x, about one ulp (subnormal x
+// too: the hardware frexp normalises them); -inf at 0, +inf at +inf and NaN
+// below 0 or at NaN (selects, no branch).
 __device__ __forceinline__ double log_pos(double x) {
     const double r = log_core<false>(x, 0.0);
     const double inf = __builtin_inf();

@@ -335,8 +335,9 @@ def test_staging_log1p_accuracy(torch_dev, sf):
 
 def test_map_log_exp_accuracy(torch_dev, sf):
     """The logarithm and exponential of the entropy-variable maps against
-    mpmath (40 digits): within 2 ulp of the result over the double range
-    (1 ulp of the smallest subnormal more where e^x is subnormal), and the
+    mpmath (40 digits): within 2 ulp of the result over the double range,
+    subnormal arguments of ln included (1 ulp of the smallest subnormal more
+    where e^x is subnormal), and the
     special values: ln 0 = -inf, ln of a negative or NaN = NaN, ln inf = inf,
     e^x = 0 or inf beyond the range, e^(+-inf) = inf, 0, e^NaN = NaN."""
     import mpmath as mp
@@ -346,7 +347,8 @@ def test_map_log_exp_accuracy(torch_dev, sf):
     tiny = 2.2250738585072014e-308
     xl = np.concatenate([rng.uniform(1e-3, 10.0, 2000), 10.0 ** rng.uniform(-307, 308, 2000),
                          1.0 + rng.uniform(-1e-6, 1e-6, 500), rng.uniform(0.5, 2.0, 1000),
-                         [1.0, 2.0, 0.5, np.nextafter(1.0, 2.0), np.nextafter(1.0, 0.0), tiny,
+                         [5e-324, 1e-320, 1e-310, 2.2250738585072009e-308,   # subnormal
+                          1.0, 2.0, 0.5, np.nextafter(1.0, 2.0), np.nextafter(1.0, 0.0), tiny,
                           1.7976931348623157e308]])
     yl = sf.diag_log(torch.from_numpy(xl).cuda()).cpu().numpy()
     for xi, yi in zip(xl, yl):
