@@ -31,20 +31,31 @@ COMMON = [
 ]
 
 # Per-file code generation options, from interleaved A/B runs on MI355X: the
-# volume, serving and curvilinear kernels are scheduled with LLVM's iterative
-# ILP strategy (volume: 1.015-1.033x over the default scheduler for every FP64
-# form measured, n = 7..12 and the pressure fix, FP32-split unchanged, fewer
-# spills at n = 9, 10; serving: 1.02x FP64 burst throughput; curvilinear:
-# 1.04x at n = 8, 1.01-1.03x at n = 4, 6, 10).  The other files keep the
-# default: it ran the transformation and entropy kernels 0.99-1.01x, and
-# crashes the compiler on the surface and dense kernels' sources.
+# FP64 volume, serving and curvilinear kernels are scheduled with LLVM's
+# iterative ILP strategy (volume: 1.015-1.033x over the default scheduler for
+# every FP64 form measured, n = 7..12 and the pressure fix, fewer spills at
+# n = 9, 10; serving: 1.02x FP64 burst throughput; curvilinear: 1.04x at
+# n = 8, 1.01-1.03x at n = 4, 6, 10).  The volume kernels' file is compiled
+# twice (SF_VOLUME_PART): the FP32-split instantiations take the
+# memory-clause strategy instead (1.01-1.02x over the default at n = 8, 9,
+# 10, where the ILP one ran 0.98-1.00x).  The other files keep the default:
+# it ran the transformation and entropy kernels 0.99-1.01x, and crashes the
+# compiler on the surface and dense kernels' sources.
 _ILP = ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]
-EXTRA = {"volume_kernels.hip": _ILP, "serve_kernels.hip": _ILP, "curv_kernels.hip": _ILP}
+_MEMCLAUSE = ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]
+# (object name, source, options) of the sources compiled with options of their own
+SPECIAL = {
+    "volume_kernels.hip": [("volume_kernels.hip", ["-DSF_VOLUME_PART=1", *_ILP]),
+                           ("volume_kernels_fp32.hip", ["-DSF_VOLUME_PART=2", *_MEMCLAUSE])],
+    "serve_kernels.hip": [("serve_kernels.hip", _ILP)],
+    "curv_kernels.hip": [("curv_kernels.hip", _ILP)],
+}
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
+def _compile(job) -> str:
+    src, name, extra = job
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [HIPCC, *COMMON, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -58,9 +69,11 @@ def _compile(src: str) -> str:
 def build(jobs: int | None = None, verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
-    jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
+    work = [(src, name, extra) for src in srcs
+            for name, extra in SPECIAL.get(os.path.basename(src), [(os.path.basename(src), [])])]
+    jobs = jobs or min(len(work), os.cpu_count() or 4, 16)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(_compile, work))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -91,11 +91,23 @@ int dispatch_n(const VolumeRequest &r) {
 
 }  // namespace dev
 
+// The build compiles this file twice: SF_VOLUME_PART 1 instantiates the FP64
+// and scalar-flux kernels and the dispatch, 2 the FP32-split kernels, each
+// with its own scheduling options (the FP32-split form runs faster with
+// another schedule); without SF_VOLUME_PART one object holds both.
+int launch_sf_volume_fp32(const VolumeRequest &r);
+
+#if !defined(SF_VOLUME_PART) || SF_VOLUME_PART == 2
+int launch_sf_volume_fp32(const VolumeRequest &r) {
+    return dev::dispatch_n<3, dev::EulerFP32Split, SF_MAX_N_EULER>(r);
+}
+#endif
+
+#if !defined(SF_VOLUME_PART) || SF_VOLUME_PART == 1
 int launch_sf_volume(const VolumeRequest &r) {
     using namespace dev;
     if (r.precision == SF_PREC_FP32_SPLIT) {
-        if (r.flux == SF_FLUX_EULER_CHANDRASHEKAR && r.d == 3)
-            return dispatch_n<3, EulerFP32Split, SF_MAX_N_EULER>(r);
+        if (r.flux == SF_FLUX_EULER_CHANDRASHEKAR && r.d == 3) return launch_sf_volume_fp32(r);
         set_error("the FP32-split form is built for the 3D Euler flux only");
         return SF_ERR_UNSUPPORTED;
     }
@@ -115,5 +127,6 @@ int launch_sf_volume(const VolumeRequest &r) {
     set_error("flux / dimension combination not built");
     return SF_ERR_UNSUPPORTED;
 }
+#endif
 
 }  // namespace sfhad

@@ -18,7 +18,7 @@ OBJ = os.path.join(ROOT, "_build", "sfhad")
 ROCM = "/opt/rocm"
 HOST_SOURCES = ["capi.cpp", "operators.cpp", "server.cpp"]
 DEVICE_OBJECTS = ["dense_kernels", "diag_kernels", "entropy_kernels", "surface_kernels", "curv_kernels",
-                  "tensor_kernels", "serve_kernels", "volume_kernels"]
+                  "tensor_kernels", "serve_kernels", "volume_kernels", "volume_kernels_fp32"]
 DRIVER = os.path.join(ROOT, "tests", "c_client", "sfhad_host_sanitized.c")
 
 
